@@ -1,0 +1,248 @@
+"""Pins of the oracle's message-passing iteration (Section 3) against things
+other than itself: the Fig. 1 topology, the algebra of the average and
+residual operators (Appendix B), a hand-traced first iteration, a two-node
+dispatch solved analytically, the Tiny DC OPF solved exactly as a reduced
+(PTDF) QP by active-set enumeration, the dual invariants, the price
+identity at the fixed point, and independence from the initial penalty."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.mp import Network, Options, Solver
+from paper_2410_17203_amd import synth
+from tests.qp_enum import solve_qp_enum
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fig1_instance():
+    rows, expect = [], None
+    for line in open(os.path.join(GOLDEN, "fig1_network.txt")):
+        line = line.strip()
+        if line.startswith("#="):
+            expect = [int(v) for v in line[2:].split()]
+            continue
+        if not line or line.startswith("#"):
+            continue
+        rows.append(line.split())
+    f = lambda v: np.asarray(v, float)
+    lines = [r for r in rows if r[1] == "line"]
+    gens = [r for r in rows if r[1] == "gen"]
+    loads = [r for r in rows if r[1] == "load"]
+    bats = [r for r in rows if r[1] == "battery"]
+    i32 = lambda v: np.asarray(v, np.int32)
+    inst = synth.Instance(
+        name="fig1", N=3, T=1, K=0,
+        line_from=i32([int(r[2]) - 1 for r in lines]), line_to=i32([int(r[3]) - 1 for r in lines]),
+        line_sus=f([1.0] * len(lines)), line_cap=f([1.0] * len(lines)), outage=i32([]),
+        gen_node=i32([int(r[2]) - 1 for r in gens]), gen_c2=f([1.0] * len(gens)),
+        gen_c1=f([1.0] * len(gens)), gen_pmin=np.zeros((len(gens), 1)),
+        gen_pmax=np.ones((len(gens), 1)), gen_ramp=np.zeros(len(gens)),
+        load_node=i32([int(r[2]) - 1 for r in loads]), load_d=np.ones((len(loads), 1)),
+        bat_node=i32([int(r[2]) - 1 for r in bats]), bat_P=f([1.0] * len(bats)),
+        bat_dur=f([4.0] * len(bats)), bat_eta=f([0.95] * len(bats)),
+        bat_alpha=f([1.0] * len(bats)))
+    return inst, expect, len(rows)
+
+
+def test_fig1_topology():
+    inst, (J, N, D, d1, d2, d3), ndev = _fig1_instance()
+    net = Network(inst)
+    assert net.J == J and net.N == N and ndev == D
+    assert net.deg.tolist() == [d1, d2, d3]
+
+
+def _dense_avg(net):
+    """A = L' diag(|n|)^-1 L with L the node-terminal incidence (App. B)."""
+    Lm = torch.zeros(net.N, net.J, dtype=torch.float64)
+    Lm[net.term_node, torch.arange(net.J)] = 1.0
+    return Lm.T @ torch.diag(1.0 / Lm.sum(1)) @ Lm
+
+
+def test_average_operator_algebra():
+    inst = synth.config("tiny")
+    net = Network(inst)
+    A = _dense_avg(net)
+    R = torch.eye(net.J, dtype=torch.float64) - A
+    torch.testing.assert_close(A @ A, A, atol=1e-14, rtol=0)
+    torch.testing.assert_close(A.T, A, atol=0, rtol=0)
+    torch.testing.assert_close(R @ R, R, atol=1e-14, rtol=0)
+    assert float((A @ R).abs().max()) < 1e-14
+    x = torch.randn(3, net.J, 2, dtype=torch.float64)
+    torch.testing.assert_close(net.avg(x), torch.einsum("ij,kjt->kit", A, x), atol=1e-14, rtol=0)
+    torch.testing.assert_close(net.resid(x), torch.einsum("ij,kjt->kit", R, x), atol=1e-14, rtol=0)
+
+
+def test_residuals_match_dense_reexpansion():
+    inst = synth.config("tiny", T=3, K=2, seed=7)
+    s = Solver(inst, Options(adapt_every=0))
+    net = s.net
+    A = _dense_avg(net)
+    R = torch.eye(net.J, dtype=torch.float64) - A
+    for _ in range(12):
+        p0, th0 = s.p.clone(), s.th.clone()
+        r = s.step()
+        dp, dth = s.p - p0, s.th - th0
+        rpp = torch.linalg.norm(torch.einsum("ij,kjt->kit", A, s.p))
+        rpt = torch.linalg.norm(torch.einsum("ij,kjt->kit", R, s.th))
+        rdp = torch.linalg.norm(torch.einsum("ij,kjt->kit", R, dp))
+        rdt = torch.linalg.norm(torch.einsum("ij,kjt->kit", A, dth))
+        for a, b in [(r.primal_p, rpp), (r.primal_th, rpt), (r.dual_p, rdp), (r.dual_th, rdt)]:
+            assert abs(a - float(b)) <= 1e-12 * max(1.0, float(b))
+
+
+def test_hand_traced_first_iteration_and_penalty_rule():
+    # Two nodes, one line (s = 1, cap = 10), G1 at node 0, G2 and a load d at
+    # node 1.  From the zero start the line sees zero targets (P = 0), both
+    # generators sit at pmin = 0 (c1 > 0) and the load draws d, so
+    # pbar = (0, -d/3) with node degrees (2, 3); u takes that value; all
+    # phases stay 0.  Hence ||pbar|| = d/sqrt(3) over the 3 terminals of
+    # node 1 and ptilde = (d/3, d/3, -2d/3) there, ||dual_p|| = rho d sqrt(2/3).
+    d = 6.0
+    inst = synth.two_node(d=d)
+    for rho0, expect_rho in [(0.01, 0.01 * 1.1), (100.0, 100.0 / 1.1), (1.0, 1.0)]:
+        s = Solver(inst, Options(rho_p=rho0, adapt_every=1, eps_relative=False))
+        r = s.step()
+        assert math.isclose(r.primal_p, d / math.sqrt(3), rel_tol=1e-14)
+        assert math.isclose(r.dual_p, rho0 * d * math.sqrt(2 / 3), rel_tol=1e-14)
+        assert r.primal_th == 0.0 and r.dual_th == 0.0
+        assert math.isclose(r.rms_primal, (d / math.sqrt(3)) / math.sqrt(2 * 5), rel_tol=1e-14)
+        # the penalty rule of Section 3.5 with mu = 2, gamma = 1.1
+        assert math.isclose(s.rho_p, expect_rho, rel_tol=1e-15)
+        assert s.rho_th == 1.0
+        # scaled prices are rescaled so that rho * u is unchanged
+        node1 = s.net.term_node == 1
+        np.testing.assert_allclose(s.rho_p * s.u[0, node1, 0].numpy(), rho0 * (-d / 3), rtol=1e-14)
+        # pbar = (0, -d/3), thetas 0, P = 0
+        assert float(s.p[0, 1, 0]) == 0.0
+        np.testing.assert_allclose(s.pbar[0, node1, 0].numpy(), -d / 3, rtol=1e-15)
+
+
+def _two_node_analytic(c2, c1, pmax, d, cap, s):
+    lo = max(0.0, d - pmax[1], -cap)
+    hi = min(pmax[0], cap, d)
+    p1 = min(max((2 * c2[1] * d + c1[1] - c1[0]) / (2 * (c2[0] + c2[1])), lo), hi)
+    p2 = d - p1
+    lmp = (2 * c2[0] * p1 + c1[0], 2 * c2[1] * p2 + c1[1])
+    return p1, p2, p1 / s, lmp
+
+
+@pytest.mark.parametrize("cap", [10.0, 1.0])
+def test_two_node_analytic_dispatch(cap):
+    c2, c1, pmax, d, sus = (0.5, 0.25), (1.0, 2.0), (5.0, 5.0), 3.0, 2.0
+    inst = synth.two_node(d=d, c2=c2, c1=c1, pmax=pmax, sus=sus, cap=cap)
+    s = Solver(inst, Options(eps=1e-10, eps_relative=False, max_iter=200000))
+    r = s.solve()
+    assert r.converged
+    p1, p2, dth, lmp = _two_node_analytic(c2, c1, pmax, d, cap, sus)
+    pg = s.dispatch()[:2, 0].numpy()
+    np.testing.assert_allclose(pg, [p1, p2], atol=1e-7)
+    # flow into the to node equals p1; angle difference = flow / susceptance
+    assert abs(float(s.p[0, 1, 0]) - p1) < 1e-7
+    assert abs(float(s.th[0, 0, 0] - s.th[0, 1, 0]) - dth) < 1e-7
+    lm = s.lmp()[:, 0].numpy()
+    np.testing.assert_allclose(lm, lmp, rtol=1e-6)
+    if cap == 1.0:
+        assert abs(lm[1] - lm[0]) > 0.5  # congestion separates the prices
+
+
+def _ptdf(N, frm, to, sus):
+    Bm = np.zeros((N, N))
+    for f, t, b in zip(frm, to, sus):
+        Bm[f, f] += b
+        Bm[t, t] += b
+        Bm[f, t] -= b
+        Bm[t, f] -= b
+    X = np.zeros((N, N))
+    X[1:, 1:] = np.linalg.inv(Bm[1:, 1:])
+    A = np.zeros((len(frm), N))
+    A[np.arange(len(frm)), frm] = 1
+    A[np.arange(len(frm)), to] = -1
+    return (sus[:, None] * A) @ X
+
+
+def _tiny_qp(inst):
+    """DC OPF (T = 1, K = 0) as a QP over generator outputs with PTDF flows."""
+    N, G = inst.N, inst.G
+    ptdf = _ptdf(N, inst.line_from, inst.line_to, inst.line_sus)
+    Cg = np.zeros((N, G))
+    Cg[inst.gen_node, np.arange(G)] = 1
+    load_inj = np.zeros(N)
+    np.subtract.at(load_inj, inst.load_node, inst.load_d[:, 0])
+    H = np.diag(2 * inst.gen_c2)
+    f = inst.gen_c1.copy()
+    E = np.ones((1, G))
+    e = np.array([inst.load_d[:, 0].sum()])
+    Cf = ptdf @ Cg
+    f0 = ptdf @ load_inj
+    C = np.vstack([np.eye(G), Cf])
+    lo = np.concatenate([inst.gen_pmin[:, 0], -inst.line_cap - f0])
+    hi = np.concatenate([inst.gen_pmax[:, 0], inst.line_cap - f0])
+    x = solve_qp_enum(H, f, E, e, C, lo, hi, max_active=G - 1)
+    return x, float(0.5 * x @ H @ x + f @ x)
+
+
+@pytest.fixture(scope="module")
+def tiny_converged():
+    inst = synth.config("tiny")
+    s = Solver(inst, Options(eps=1e-8, max_iter=100000))
+    r = s.solve()
+    return inst, s, r
+
+
+def test_tiny_matches_exact_qp(tiny_converged):
+    inst, s, r = tiny_converged
+    assert r.converged
+    x, obj = _tiny_qp(inst)
+    assert abs(r.objective - obj) <= 1e-5 * abs(obj)
+    np.testing.assert_allclose(s.dispatch()[:inst.G, 0].numpy(), x, atol=2e-5)
+
+
+def test_tiny_price_identity(tiny_converged):
+    # At a fixed point of step 2 with pbar = 0 an interior generator satisfies
+    # 2 c2 p + c1 + (K+1) rho_p avg_k u_k = 0, i.e. its marginal cost equals
+    # the locational price -rho_p sum_k u_k.
+    inst, s, r = tiny_converged
+    pg = s.dispatch()[:inst.G, 0].numpy()
+    lmp = s.lmp()[:, 0].numpy()
+    interior = (pg > 1e-4) & (pg < inst.gen_pmax[:, 0] - 1e-4)
+    assert interior.any()
+    mc = 2 * inst.gen_c2 * pg + inst.gen_c1
+    np.testing.assert_allclose(mc[interior], lmp[inst.gen_node[interior]], rtol=1e-5)
+
+
+def test_dual_invariants_hold_along_iterations():
+    inst = synth.config("tiny", T=4, K=3, seed=5, B=2)
+    s = Solver(inst, Options())
+    for _ in range(40):
+        s.step()
+        # u constant within every node (u tilde = 0), v sums to zero per node
+        assert float(s.net.resid(s.u).abs().max()) <= 1e-13 * max(1.0, float(s.u.abs().max()))
+        vs = s.net.node_sum(s.v)
+        assert float(vs.abs().max()) <= 1e-12 * max(1.0, float(s.v.abs().sum()))
+
+
+def test_noop_contingencies_reach_base_solution():
+    base = synth.config("tiny")
+    a = Solver(base, Options(eps=1e-8, max_iter=100000))
+    ra = a.solve()
+    cont = base.copy()
+    cont.K = 2
+    cont.outage = np.array([-1, -1], np.int32)
+    b = Solver(cont, Options(eps=1e-8, max_iter=100000))
+    rb = b.solve()
+    assert ra.converged and rb.converged
+    np.testing.assert_allclose(b.dispatch().numpy(), a.dispatch().numpy(), atol=1e-5)
+    assert abs(ra.objective - rb.objective) <= 1e-6 * abs(ra.objective)
+
+
+def test_solution_independent_of_initial_penalty(tiny_converged):
+    inst, s, r = tiny_converged
+    b = Solver(inst, Options(eps=1e-8, max_iter=100000, rho_p=4.0, rho_theta=0.3))
+    rb = b.solve()
+    assert rb.converged
+    np.testing.assert_allclose(b.dispatch().numpy(), s.dispatch().numpy(), atol=2e-5)
+    np.testing.assert_allclose(b.lmp().numpy(), s.lmp().numpy(), rtol=1e-4)
