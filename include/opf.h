@@ -1,0 +1,211 @@
+/*
+ * opf.h - C ABI of the MI355X (gfx950) proximal message-passing solver for
+ * contingency-constrained DC optimal power flow.
+ *
+ * Method: Degleris, El Gamal, Rajagopal, "GPU Accelerated Security
+ * Constrained Optimal Power Flow" (arXiv 2410.17203).  The problem is the
+ * contingency-constrained OPF of Section 2.3 on the device-node model of
+ * Section 2; the iteration is the message-passing form of ADMM of Section
+ * 3.2 with the stopping rule of Section 3.3 (eq. converge) and the adaptive
+ * penalty of Section 3.5.
+ *
+ * Conventions for every function:
+ *   - the return value is an opf_status; nothing is thrown and nothing
+ *     exits across this boundary; opf_last_error() describes a failure;
+ *   - all host arrays passed in are owned by the caller and only read
+ *     during the call (they are copied);
+ *   - device memory is never allocated by the library: the caller passes
+ *     one workspace (any device allocation, e.g. a PyTorch tensor) whose
+ *     size opf_workspace_size() reports; the library borrows it until
+ *     opf_destroy();
+ *   - all device work is enqueued on the stream given in opf_options and
+ *     is asynchronous unless a function says it synchronises;
+ *   - a context is not thread-safe; use one context per stream.
+ */
+#ifndef OPF_H
+#define OPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct opf_ctx opf_ctx;
+
+typedef enum {
+  OPF_OK = 0,
+  OPF_NOT_CONVERGED = 1,   /* informational: max_iter reached first      */
+  OPF_E_INVALID = -1,      /* bad argument or bad network data           */
+  OPF_E_OOM = -2,          /* workspace smaller than required            */
+  OPF_E_HIP = -3,          /* a HIP runtime call failed                  */
+  OPF_E_STATE = -4,        /* call out of order (e.g. iterate before load) */
+  OPF_E_NUMERIC = -5       /* a residual became NaN or infinite          */
+} opf_status;
+
+typedef enum { OPF_F64 = 0, OPF_F32 = 1, OPF_BF16 = 2 } opf_dtype;
+
+/* Solver options.  Defaults (opf_default_options) follow Section 5.2:
+ * rho_p = rho_theta = 1, mu = 2, gamma = 1.1 every 10 iterations, no
+ * over-relaxation; 10 inner iterations for time-coupled devices (Section 4.5). */
+typedef struct {
+  int32_t state_dtype;        /* OPF_F64 or OPF_F32: storage and arithmetic of the
+                                 iterate; norms and the objective are always FP64 */
+  int32_t dual_dtype;         /* storage of the line phase duals: equal to
+                                 state_dtype, or OPF_BF16 with an F32 state      */
+  double rho_p, rho_theta;    /* initial penalties (Section 3.2)                 */
+  double mu, gamma;           /* adaptive penalty rule (Section 3.5)             */
+  int32_t adapt_every;        /* iterations between penalty updates; 0 = fixed   */
+  double eps;                 /* tolerance of eq. converge on the RMS residuals  */
+  int32_t eps_relative;       /* 1: eps is scaled by the RMS load demand         */
+  int32_t max_iter, min_iter; /* iteration limits of opf_solve                   */
+  int32_t block_iters;        /* iterations per captured graph block in opf_solve */
+  int32_t check_every;        /* residuals every check_every iterations; must
+                                 divide adapt_every                              */
+  int32_t inner_iters;        /* inner ADMM iterations of the time-coupled prox  */
+  double inner_omega_scale;   /* inner penalty omega = scale * (K+1) rho_p       */
+  int32_t polish_fp64;        /* F32 state: opf_solve switches the iterate to
+                                 FP64 once the residual is within polish_factor
+                                 of the tolerance                                */
+  double polish_factor;       /* [1.2] switch point, as a multiple of eps        */
+  int32_t use_graphs;         /* 1: opf_solve replays captured graph blocks      */
+  void* hip_stream;           /* hipStream_t for all work; NULL = null stream    */
+} opf_options;
+
+/* Fills *opt with the defaults above (F64 state, eps = 1e-3 relative,
+ * max_iter 10000, block_iters 50, check_every 1, polish on at 1.2 eps,
+ * graphs on). */
+void opf_default_options(opf_options* opt);
+
+/* One network (Section 2): nodes 0..N-1, T periods, K contingencies.
+ * Line l joins terminal 1 at node line_from[l] to terminal 2 at line_to[l];
+ * its flow into the to node is susceptance * (phase_from - phase_to)
+ * (Section 2.1, AC line).  Contingency k in 1..K zeroes the capacity and
+ * susceptance of line outage[k-1] (Section 2.3, N-1 example); an outage of
+ * -1 leaves the network unchanged.  Per-period arrays are row-major
+ * [device][t].  Loads store demand d >= 0 and inject -d.  gen_ramp[g] <= 0
+ * or infinite means no ramp limit; otherwise |p_{t+1} - p_t| <= gen_ramp[g]
+ * for T > 1.  Battery parameters are power P, duration (energy = dur * P),
+ * charge efficiency eta in (0, 1] and discharge cost alpha >= 0 (Section
+ * 2.1, battery).  Every node needs at least one terminal.  Host arrays,
+ * caller-owned, copied by opf_load_network. */
+typedef struct {
+  int32_t N, T, K;
+  int32_t L;
+  const int32_t *line_from, *line_to;
+  const double *line_sus, *line_cap;      /* sus > 0, cap >= 0               */
+  const int32_t* outage;                  /* K entries, distinct or -1       */
+  int32_t G;
+  const int32_t* gen_node;
+  const double *gen_c2, *gen_c1;          /* c2 > 0                          */
+  const double *gen_pmin, *gen_pmax;      /* G*T, pmin <= pmax               */
+  const double* gen_ramp;                 /* G                               */
+  int32_t D;
+  const int32_t* load_node;
+  const double* load_d;                   /* D*T                             */
+  int32_t B;
+  const int32_t* bat_node;
+  const double *bat_P, *bat_dur, *bat_eta, *bat_alpha;
+} opf_network;
+
+/* Residual record of one iteration (Section 3.3).  Norms are 2-norms over
+ * all terminal copies of all contingencies and periods; rms_* divide by
+ * sqrt(2 J T (K+1)); dual norms include the penalty factor. */
+typedef struct {
+  int64_t iter;                 /* iterations completed                      */
+  double primal_p, primal_theta; /* ||pbar||, ||theta tilde||                */
+  double dual_p, dual_theta;    /* rho_p ||d ptilde||, rho_theta ||d thetabar|| */
+  double rms_primal, rms_dual;
+  double threshold;             /* effective eps                             */
+  double objective;             /* sum of generator and battery costs        */
+  double rho_p, rho_theta;      /* penalties used by this iteration          */
+  int32_t converged;
+  int32_t precision;            /* opf_dtype of the iterate                  */
+} opf_resid;
+
+/* Creates a context.  *out receives the handle; opt is copied. */
+opf_status opf_create(const opf_options* opt, opf_ctx** out);
+
+/* Device bytes the workspace must provide for net (validates net). */
+opf_status opf_workspace_size(opf_ctx* ctx, const opf_network* net, size_t* bytes);
+
+/* Validates and copies the network into the workspace (d_workspace: device
+ * pointer, 256-byte aligned, at least opf_workspace_size bytes) and resets
+ * the iterate to the all-zero start of Section 3.4.  Synchronises the
+ * stream.  Invalid data returns OPF_E_INVALID and leaves ctx unchanged. */
+opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
+                            void* d_workspace, size_t bytes);
+
+/* Enqueues n_iters message-passing iterations (Section 3.2 steps 1-3 plus
+ * residuals and the adaptive penalty).  Asynchronous.  Iterations after
+ * convergence or max_iter are skipped on the device. */
+opf_status opf_iterate(opf_ctx* ctx, int32_t n_iters);
+
+/* Iterates until eq. converge holds or max_iter; synchronises.  Returns
+ * OPF_OK or OPF_NOT_CONVERGED and the last residual record in *out. */
+opf_status opf_solve(opf_ctx* ctx, opf_resid* out);
+
+/* Synchronises the stream and returns the last residual record. */
+opf_status opf_residuals(opf_ctx* ctx, opf_resid* out);
+
+/* Copies up to max records of the residual history (oldest first, at most
+ * the last 4096 iterations) into out; *n receives the count.  Synchronises. */
+opf_status opf_residual_history(opf_ctx* ctx, opf_resid* out, int32_t max, int32_t* n);
+
+/* Fields of the iterate in the paper's layout (Section 4.1), FP64. */
+typedef enum {
+  OPF_FIELD_P = 0,      /* line flow p2 into the to node    [K+1][L][T] */
+  OPF_FIELD_TH1 = 1,    /* line phase at terminal 1         [K+1][L][T] */
+  OPF_FIELD_TH2 = 2,    /* line phase at terminal 2         [K+1][L][T] */
+  OPF_FIELD_V1 = 3,     /* scaled phase dual, terminal 1    [K+1][L][T] */
+  OPF_FIELD_V2 = 4,     /* scaled phase dual, terminal 2    [K+1][L][T] */
+  OPF_FIELD_U = 5,      /* scaled power dual (node-constant) [K+1][N][T] */
+  OPF_FIELD_PBAR = 6,   /* node average power               [K+1][N][T] */
+  OPF_FIELD_THBAR = 7,  /* node average phase               [K+1][N][T] */
+  OPF_FIELD_PNC = 8,    /* generator, load, battery power   [G+D+B][T]  */
+  OPF_FIELD_THNC = 9,   /* their phases                     [G+D+B][T]  */
+  OPF_FIELD_VNC = 10    /* their phase duals averaged over k [G+D+B][T] */
+} opf_field;
+
+/* Number of doubles in a field. */
+opf_status opf_field_size(opf_ctx* ctx, int32_t field, size_t* count);
+
+/* Writes one field of the current iterate, as FP64 in the layout above,
+ * to the device buffer d_dst (count doubles).  Enqueued on the stream. */
+opf_status opf_get_field(opf_ctx* ctx, int32_t field, double* d_dst, size_t count);
+
+/* Enables (1) or disables (0) per-kernel HIP-event timing of subsequent
+ * opf_iterate calls; enabling clears the accumulated times. */
+opf_status opf_set_timing(opf_ctx* ctx, int32_t enable);
+
+/* Kernel classes timed by opf_set_timing. */
+typedef enum {
+  OPF_KERNEL_DEVICES = 0,   /* generator, load, battery prox (step 2)   */
+  OPF_KERNEL_SWEEP = 1,     /* line prox, node averages, price update
+                               (steps 1 and 3, fused)                   */
+  OPF_KERNEL_FINALIZE = 2,  /* residual norms, stopping, penalty        */
+  OPF_KERNEL_RESCALE = 3,   /* dual rescale after a penalty change      */
+  OPF_KERNEL_COUNT = 4
+} opf_kernel;
+
+/* Synchronises and returns, per kernel class, the summed milliseconds and
+ * the launch count since timing was enabled (arrays of OPF_KERNEL_COUNT). */
+opf_status opf_kernel_times(opf_ctx* ctx, double* ms, int64_t* launches);
+
+/* Algorithmic device bytes one launch of a kernel class moves for the
+ * loaded network and current precision (used for roofline reporting). */
+opf_status opf_kernel_bytes(opf_ctx* ctx, int32_t kernel, double* bytes);
+
+/* Text of the last failure on ctx (or of opf_create when ctx is NULL). */
+const char* opf_last_error(opf_ctx* ctx);
+
+/* Releases host resources and captured graphs; the workspace is the
+ * caller's to free afterwards.  Synchronises the stream. */
+void opf_destroy(opf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPF_H */

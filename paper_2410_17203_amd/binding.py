@@ -1,0 +1,301 @@
+"""Python binding of the C ABI in include/opf.h (ctypes; marshalling only).
+
+PyTorch supplies the device workspace (one uint8 tensor) and the HIP stream;
+every step of the iteration runs in the HIP library.  There is no fallback:
+if libopf.so is missing or no GPU is visible the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_int32, c_int64,
+                    c_size_t, c_void_p)
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("OPF_LIB", os.path.join(HERE, "_lib", "libopf.so"))
+HEADER = os.path.join(os.path.dirname(HERE), "include", "opf.h")
+
+F64, F32, BF16 = 0, 1, 2
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+
+STATUS = {0: "OPF_OK", 1: "OPF_NOT_CONVERGED", -1: "OPF_E_INVALID", -2: "OPF_E_OOM",
+          -3: "OPF_E_HIP", -4: "OPF_E_STATE", -5: "OPF_E_NUMERIC"}
+
+FIELDS = {"P": 0, "TH1": 1, "TH2": 2, "V1": 3, "V2": 4, "U": 5, "PBAR": 6, "THBAR": 7,
+          "PNC": 8, "THNC": 9, "VNC": 10}
+KERNELS = ["devices", "sweep", "finalize", "rescale"]
+
+
+class Options(Structure):
+    _fields_ = [
+        ("state_dtype", c_int32), ("dual_dtype", c_int32),
+        ("rho_p", c_double), ("rho_theta", c_double),
+        ("mu", c_double), ("gamma", c_double),
+        ("adapt_every", c_int32),
+        ("eps", c_double), ("eps_relative", c_int32),
+        ("max_iter", c_int32), ("min_iter", c_int32),
+        ("block_iters", c_int32), ("check_every", c_int32),
+        ("inner_iters", c_int32), ("inner_omega_scale", c_double),
+        ("polish_fp64", c_int32), ("polish_factor", c_double), ("use_graphs", c_int32),
+        ("hip_stream", c_void_p),
+    ]
+
+
+class Network(Structure):
+    _fields_ = [
+        ("N", c_int32), ("T", c_int32), ("K", c_int32),
+        ("L", c_int32), ("line_from", POINTER(c_int32)), ("line_to", POINTER(c_int32)),
+        ("line_sus", POINTER(c_double)), ("line_cap", POINTER(c_double)),
+        ("outage", POINTER(c_int32)),
+        ("G", c_int32), ("gen_node", POINTER(c_int32)),
+        ("gen_c2", POINTER(c_double)), ("gen_c1", POINTER(c_double)),
+        ("gen_pmin", POINTER(c_double)), ("gen_pmax", POINTER(c_double)),
+        ("gen_ramp", POINTER(c_double)),
+        ("D", c_int32), ("load_node", POINTER(c_int32)), ("load_d", POINTER(c_double)),
+        ("B", c_int32), ("bat_node", POINTER(c_int32)),
+        ("bat_P", POINTER(c_double)), ("bat_dur", POINTER(c_double)),
+        ("bat_eta", POINTER(c_double)), ("bat_alpha", POINTER(c_double)),
+    ]
+
+
+class Resid(Structure):
+    _fields_ = [
+        ("iter", c_int64),
+        ("primal_p", c_double), ("primal_theta", c_double),
+        ("dual_p", c_double), ("dual_theta", c_double),
+        ("rms_primal", c_double), ("rms_dual", c_double),
+        ("threshold", c_double), ("objective", c_double),
+        ("rho_p", c_double), ("rho_theta", c_double),
+        ("converged", c_int32), ("precision", c_int32),
+    ]
+
+    def as_dict(self) -> Dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class OpfError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libopf.so and declares every entry point's signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OpfError(f"{path} not built; run paper_2410_17203_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "opf_default_options": (None, [POINTER(Options)]),
+        "opf_create": (c_int32, [POINTER(Options), POINTER(c_void_p)]),
+        "opf_workspace_size": (c_int32, [P, POINTER(Network), POINTER(c_size_t)]),
+        "opf_load_network": (c_int32, [P, POINTER(Network), c_void_p, c_size_t]),
+        "opf_iterate": (c_int32, [P, c_int32]),
+        "opf_solve": (c_int32, [P, POINTER(Resid)]),
+        "opf_residuals": (c_int32, [P, POINTER(Resid)]),
+        "opf_residual_history": (c_int32, [P, POINTER(Resid), c_int32, POINTER(c_int32)]),
+        "opf_field_size": (c_int32, [P, c_int32, POINTER(c_size_t)]),
+        "opf_get_field": (c_int32, [P, c_int32, c_void_p, c_size_t]),
+        "opf_set_timing": (c_int32, [P, c_int32]),
+        "opf_kernel_times": (c_int32, [P, POINTER(c_double), POINTER(c_int64)]),
+        "opf_kernel_bytes": (c_int32, [P, c_int32, POINTER(c_double)]),
+        "opf_last_error": (c_char_p, [P]),
+        "opf_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_options() -> Options:
+    o = Options()
+    load_library().opf_default_options(byref(o))
+    return o
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class NetworkArrays:
+    """Keeps the marshalled host arrays alive for the lifetime of a call."""
+
+    def __init__(self, inst):
+        i32, f64 = np.int32, np.float64
+        T = int(inst.T)
+        self.keep = []
+
+        def p(a, dt, ctype):
+            a = _arr(a, dt)
+            self.keep.append(a)
+            return a.ctypes.data_as(POINTER(ctype))
+
+        n = Network()
+        n.N, n.T, n.K = int(inst.N), T, int(inst.K)
+        n.L = len(inst.line_from)
+        n.line_from = p(inst.line_from, i32, c_int32)
+        n.line_to = p(inst.line_to, i32, c_int32)
+        n.line_sus = p(inst.line_sus, f64, c_double)
+        n.line_cap = p(inst.line_cap, f64, c_double)
+        n.outage = p(inst.outage, i32, c_int32)
+        n.G = len(inst.gen_node)
+        n.gen_node = p(inst.gen_node, i32, c_int32)
+        n.gen_c2 = p(inst.gen_c2, f64, c_double)
+        n.gen_c1 = p(inst.gen_c1, f64, c_double)
+        n.gen_pmin = p(np.reshape(inst.gen_pmin, (n.G, T)), f64, c_double)
+        n.gen_pmax = p(np.reshape(inst.gen_pmax, (n.G, T)), f64, c_double)
+        n.gen_ramp = p(inst.gen_ramp, f64, c_double)
+        n.D = len(inst.load_node)
+        n.load_node = p(inst.load_node, i32, c_int32)
+        n.load_d = p(np.reshape(inst.load_d, (n.D, T)), f64, c_double)
+        n.B = len(inst.bat_node)
+        n.bat_node = p(inst.bat_node, i32, c_int32)
+        n.bat_P = p(inst.bat_P, f64, c_double)
+        n.bat_dur = p(inst.bat_dur, f64, c_double)
+        n.bat_eta = p(inst.bat_eta, f64, c_double)
+        n.bat_alpha = p(inst.bat_alpha, f64, c_double)
+        self.net = n
+
+
+def _options(dtype: str, dual_dtype: Optional[str], stream_ptr: int, **kw) -> Options:
+    o = default_options()
+    o.state_dtype = DTYPES[dtype]
+    o.dual_dtype = DTYPES[dual_dtype] if dual_dtype else DTYPES[dtype]
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, float(v) if isinstance(getattr(o, k), float) else int(v))
+    o.hip_stream = c_void_p(stream_ptr)
+    return o
+
+
+class Solver:
+    """One instance loaded on one GPU.
+
+    dtype: 'f64' or 'f32' iterate; dual_dtype 'bf16' stores the line phase
+    duals in BF16 (with dtype 'f32').  Keyword options map onto opf_options.
+    """
+
+    def __init__(self, inst, dtype: str = "f64", dual_dtype: Optional[str] = None,
+                 device: str = "cuda:0", **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise OpfError("no GPU visible: the HIP library has no CPU path")
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.opt = _options(dtype, dual_dtype, self.stream.cuda_stream, **opts)
+        ctx = c_void_p()
+        self._check(self.lib.opf_create(byref(self.opt), byref(ctx)), None)
+        self.ctx = ctx
+        arrays = NetworkArrays(inst)
+        nbytes = c_size_t()
+        self._check(self.lib.opf_workspace_size(self.ctx, byref(arrays.net), byref(nbytes)))
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.opf_load_network(self.ctx, byref(arrays.net),
+                                              c_void_p(self.ws.data_ptr()), nbytes))
+        self.N, self.T, self.K = int(inst.N), int(inst.T), int(inst.K)
+        self.L = len(inst.line_from)
+        self.Jnc = len(inst.gen_node) + len(inst.load_node) + len(inst.bat_node)
+        self.workspace_bytes = int(nbytes.value)
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st, ctx="self"):
+        if st in (0, 1):
+            return st
+        c = self.ctx if ctx == "self" else None
+        msg = self.lib.opf_last_error(c)
+        raise OpfError(f"{STATUS.get(st, st)}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            self.lib.opf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- iteration ---------------------------------------------------------------
+    def iterate(self, n: int):
+        self._check(self.lib.opf_iterate(self.ctx, int(n)))
+
+    def solve(self) -> Dict:
+        r = Resid()
+        st = self._check(self.lib.opf_solve(self.ctx, byref(r)))
+        d = r.as_dict()
+        d["status"] = STATUS[st]
+        return d
+
+    def residuals(self) -> Dict:
+        r = Resid()
+        self._check(self.lib.opf_residuals(self.ctx, byref(r)))
+        return r.as_dict()
+
+    def history(self, max_records: int = 4096) -> List[Dict]:
+        buf = (Resid * max_records)()
+        n = c_int32()
+        self._check(self.lib.opf_residual_history(self.ctx, buf, max_records, byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # -- state -------------------------------------------------------------------
+    def field_device(self, name: str):
+        """One field of the iterate as a float64 device tensor in the paper's
+        layout ([K+1][L][T], [K+1][N][T] or [G+D+B][T])."""
+        torch = self.torch
+        fid = FIELDS[name]
+        cnt = c_size_t()
+        self._check(self.lib.opf_field_size(self.ctx, fid, byref(cnt)))
+        out = torch.empty(int(cnt.value), dtype=torch.float64, device=self.device)
+        self._check(self.lib.opf_get_field(self.ctx, fid, c_void_p(out.data_ptr()), cnt))
+        self.stream.synchronize()
+        Kp = self.K + 1
+        shape = {0: (Kp, self.L, self.T), 5: (Kp, self.N, self.T), 8: (self.Jnc, self.T)}
+        key = 0 if fid <= 4 else (5 if fid <= 7 else 8)
+        return out.reshape(shape[key])
+
+    def field(self, name: str):
+        """One field of the iterate as a float64 CPU tensor."""
+        return self.field_device(name).cpu()
+
+    def state(self) -> Dict:
+        return {k: self.field(k) for k in FIELDS}
+
+    # -- timing --------------------------------------------------------------------
+    def set_timing(self, enable: bool):
+        self._check(self.lib.opf_set_timing(self.ctx, 1 if enable else 0))
+
+    def kernel_times(self) -> Dict[str, Dict]:
+        ms = (c_double * 4)()
+        n = (c_int64 * 4)()
+        self._check(self.lib.opf_kernel_times(self.ctx, ms, n))
+        return {KERNELS[i]: {"ms": ms[i], "launches": n[i]} for i in range(4)}
+
+    def kernel_bytes(self, kernel: str) -> float:
+        b = c_double()
+        self._check(self.lib.opf_kernel_bytes(self.ctx, KERNELS.index(kernel), byref(b)))
+        return b.value
+
+
+def header_functions(path: str = HEADER) -> List[str]:
+    """Names of the functions include/opf.h declares."""
+    import re
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(opf_[a-z_]+)\s*\(", txt)))

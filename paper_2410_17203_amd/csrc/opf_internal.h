@@ -1,0 +1,153 @@
+// Internal device-side data structures of the message-passing library.
+//
+// Data layout in HBM (one instance):
+//   line arrays   [T][L][Kpp]  flow P, mean phase Tm, phase duals V1, V2
+//   node arrays   [T][N][Kpp]  price U, W = pbar + U, thetabar TB
+//   node averages [N][T]       mean over contingencies of W and TB
+//   device arrays [Jnc][T]     generator/load/battery power, phase and the
+//                              contingency-averaged phase dual
+// The contingency index k is innermost (padded to Kpp, a multiple of 4) so
+// that every gather of a node slab by a line, and every line read by a node,
+// is a contiguous run of Kp values.  Time is outermost so that a sweep over
+// one period's nodes touches only that period's line and node slabs.  A
+// line's two phases are stored as their mean Tm; the half difference is
+// P / (2 b) for a live line and, for the one outaged line of contingency k,
+// a separate [T][Kpp] array Td.  Line and node arrays are double-buffered
+// (the sweep reads one buffer and writes the other).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace opf {
+
+constexpr int kBlock = 256;      // threads per block of every kernel
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kRing = 4096;      // residual records kept on the device
+
+struct bf16_t {
+  uint16_t u;
+};
+
+// Device control block: penalties, pending dual rescale, counters, flags.
+struct Ctl {
+  double rho_p, rho_th;   // penalties used by the next iteration
+  double su, sv;          // pending rescale of U (and inner duals) and of V
+  double eps_eff;         // effective tolerance on the RMS residuals
+  double rms_norm;        // sqrt(2 J T (K+1))
+  double mu, gamma;       // adaptive penalty rule
+  int32_t iter;           // iterations completed
+  int32_t launches;       // finalize launches reached (completed or skipped)
+  int32_t scale_iter;     // value of launches when su/sv were last set
+  int32_t done;           // converged, max_iter or numeric failure
+  int32_t converged;
+  int32_t numeric_bad;
+  int32_t adapt_every, check_every, max_iter, min_iter;
+  int32_t precision;      // 0 = FP64, 1 = FP32
+  int32_t cur;            // buffer holding the current iterate (0 or 1)
+};
+
+// Residual record written by the finalize kernel.
+struct Rec {
+  double primal_p, primal_th, dual_p, dual_th;
+  double rms_primal, rms_dual, threshold, objective, rho_p, rho_th;
+  int64_t iter;
+  int32_t converged, precision;
+};
+
+// Precision-independent network data (device pointers into the workspace).
+struct Topo {
+  int32_t N, T, K, Kp, Kpp, L, G, D, B, Jnc, nR;
+  const int32_t* line_from;
+  const int32_t* line_to;
+  const double* sus;
+  const double* cap;
+  const int32_t* outage_k;    // [Kpp]: line removed in contingency k, -1 none
+  const int32_t* node_lptr;   // [N+1] CSR over line terminals
+  const int2* node_lterm;     // (2 l + end, node at the line's other end)
+  const int32_t* node_nptr;   // [N+1] CSR over generator/load/battery ids
+  const int32_t* node_nterm;
+  const double* deg;          // [N] terminals per node
+  const int32_t* nc_node;     // [Jnc]
+  const int32_t* ramp_idx;    // [G] index into ramp inner state, -1 = none
+  const double* gen_c2;
+  const double* gen_c1;
+  const double* gen_pmin;     // [G][T]
+  const double* gen_pmax;
+  const double* gen_ramp;
+  const double* load_d;       // [D][T]
+  const double* bat_P;
+  const double* bat_dur;
+  const double* bat_eta;
+  const double* bat_alpha;
+};
+
+// Double-buffered part of the iterate.
+template <typename R, typename VT>
+struct Buf {
+  R* P;
+  R* Tm;
+  VT* V1;
+  VT* V2;
+  R* Td;      // [T][Kpp]
+  R* U;
+  R* W;
+  R* TB;
+};
+
+// Iterate in one precision.  R: arithmetic/storage type, VT: storage of V.
+template <typename R, typename VT>
+struct State {
+  Buf<R, VT> buf[2];
+  R* avgW;    // [N][T]
+  R* avgTB;
+  R* pnc;     // [Jnc][T]
+  R* thnc;
+  R* vbar;
+  R* ramp_st; // 4 arrays [nR][T]: beta_box, lambda_box, beta_ramp, lambda_ramp
+  R* bat_st;  // 6 arrays [B][T]: beta/lambda for charge, discharge, state of charge
+};
+
+// Launch geometry and scratch shared by all kernels of one instance.
+struct Geom {
+  int32_t nv;             // 16-byte vectors per [Kpp] row
+  int32_t n_nc_blocks;    // k_devices grid: 4 devices per block
+  int32_t lanes_per_row;  // lanes per (period, node) row (power of 2, <= 64)
+  int32_t rows_per_grp;   // rows per block step: 4 waves * (64 / lanes_per_row)
+  int64_t n_grps;         // ceil(N*T / rows_per_grp), rows ordered t * N + n
+  int32_t n_sweep_blocks; // multiple of 8
+  int32_t inner_iters;
+  double omega_scale;
+  double* part_sweep;     // [n_sweep_blocks][5]
+  double* part_nc;        // [n_nc_blocks][2]
+  Ctl* ctl;
+  Rec* ring;
+};
+
+template <typename R, typename VT>
+struct KArgs {
+  Topo tp;
+  State<R, VT> st;
+  Geom g;
+};
+
+// Host-side launchers (opf_kernels.hip).
+template <typename R, typename VT>
+int sweep_resident_blocks();
+template <typename R, typename VT>
+void launch_devices(const KArgs<R, VT>& a, hipStream_t s);
+template <typename R, typename VT>
+void launch_sweep(const KArgs<R, VT>& a, hipStream_t s);
+template <typename R, typename VT>
+void launch_finalize(const KArgs<R, VT>& a, hipStream_t s);
+template <typename R, typename VT>
+void launch_rescale(const KArgs<R, VT>& a, hipStream_t s);
+template <typename R, typename VT>
+void launch_export(const KArgs<R, VT>& a, int field, double* dst, hipStream_t s);
+// Widening copy of a FP32 iterate into a FP64 iterate (polishing).
+template <typename VT>
+void launch_widen(const KArgs<float, VT>& src, const KArgs<double, double>& dst, hipStream_t s);
+
+}  // namespace opf

@@ -1,0 +1,1068 @@
+// HIP kernels (gfx950) of one proximal message-passing iteration for
+// contingency-constrained DC OPF (arXiv 2410.17203, Section 3.2):
+//
+//   k_devices  step 2: prox of every generator, load and battery at the
+//              contingency-averaged targets, one device per wavefront (the
+//              time-coupled ones by an inner ADMM whose tridiagonal solves
+//              are wavefront scans over the horizon).
+//   k_sweep    steps 1 and 3 fused, one (period, node) row of contingencies
+//              per lane group: every line at the node is proxed from the
+//              previous iterate (both end nodes compute it identically, the
+//              from node stores it), then the node averages pbar, thetabar
+//              are formed as CSR-by-node segmented sums in a fixed order (no
+//              atomics), the price u += pbar is updated, and the contingency
+//              averages for step 2 and the FP64 residual partials of Section
+//              3.3 are produced.  The iterate is double-buffered; the device
+//              control block says which buffer is current.
+//   k_finalize FP64 residual norms, the stopping test of eq. converge and the
+//              adaptive penalty of Section 3.5, all on the device.
+//   k_rescale  u <- (rho_old / rho_new) u after a penalty change.
+//
+// The path is sparse and elementwise (no dense contraction), so it runs on
+// the vector ALUs and is bound by HBM bandwidth.
+#include "opf_internal.h"
+
+// 1: rows read once per sweep (own price row) and all rows written by it use
+// non-temporal loads and stores, so they do not evict from L2 the line and
+// node rows that neighbouring nodes read again shortly after.
+#ifndef OPF_NT
+#define OPF_NT 1
+#endif
+// Line terminals of a node taken per step of the sweep (1 or 2): all loads of
+// a step are issued before any of them is used.
+#ifndef OPF_SWEEP_BATCH
+#define OPF_SWEEP_BATCH 1
+#endif
+// Minimum waves per SIMD requested for the sweep (0: compiler's choice); a
+// higher value caps its registers so that more waves hide memory latency.
+#ifndef OPF_SWEEP_WAVES
+#define OPF_SWEEP_WAVES 0
+#endif
+#if OPF_SWEEP_WAVES > 0
+#define OPF_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(OPF_SWEEP_WAVES)))
+#else
+#define OPF_SWEEP_ATTR
+#endif
+
+namespace opf {
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) Vec {
+  T x[N];
+};
+
+// Storage conversion of the phase duals (FP32 arithmetic on BF16 storage).
+template <typename VT, typename R>
+struct DIO;
+template <typename R>
+struct DIO<R, R> {
+  __device__ static R in(R v) { return v; }
+  __device__ static R out(R v) { return v; }
+};
+template <>
+struct DIO<bf16_t, float> {
+  __device__ static float in(bf16_t v) { return __uint_as_float(uint32_t(v.u) << 16); }
+  __device__ static bf16_t out(float f) {
+    uint32_t u = __float_as_uint(f);
+    bf16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      r.u = uint16_t((u >> 16) | 0x40u);
+      return r;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    r.u = uint16_t(u >> 16);
+    return r;
+  }
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// 16- or 8-byte vector load/store that bypasses L2 retention when OPF_NT.
+template <typename V>
+__device__ inline V ld_stream(const V* p) {
+  static_assert(sizeof(V) == 16 || sizeof(V) == 8, "vector size");
+#if OPF_NT
+  if constexpr (sizeof(V) == 16) {
+    return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+  } else {
+    return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p)));
+  }
+#else
+  return *p;
+#endif
+}
+template <typename V>
+__device__ inline void st_stream(V* p, const V& v) {
+  static_assert(sizeof(V) == 16 || sizeof(V) == 8, "vector size");
+#if OPF_NT
+  if constexpr (sizeof(V) == 16) {
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(p));
+  } else {
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2*>(p));
+  }
+#else
+  *p = v;
+#endif
+}
+
+template <typename R>
+__device__ inline R clampv(R x, R lo, R hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by id.  Work items [0, n)
+// are split into 8 contiguous ranges, one per XCD, and the nb/8 blocks of an
+// XCD sweep their range together as one moving front (block j of the XCD
+// takes items j, j + nb/8, ...), so the line and node rows that neighbouring
+// items share are reused from that XCD's L2 shortly after first use.  nb must
+// be a multiple of 8.
+struct Sweep {
+  int64_t first, end;
+  int step;
+};
+#ifndef OPF_XCD_SWEEP
+#define OPF_XCD_SWEEP 1
+#endif
+__device__ inline Sweep xcd_sweep(int b, int nb, int64_t n) {
+  Sweep s;
+#if OPF_XCD_SWEEP
+  const int x = b & 7, j = b >> 3, per = nb >> 3;
+  s.first = n * x / 8 + j;
+  s.end = n * (x + 1) / 8;
+  s.step = per;
+#else
+  s.first = b;
+  s.end = n;
+  s.step = nb;
+#endif
+  return s;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Deterministic block sum; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / kWave; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront linear recurrences.  Element t of a length-T sequence lives in
+// lane t / E, slot t % E.  fwd: x_t = a_t x_{t-1} + b_t with x_{-1} = 0;
+// bwd: x_t = a_t x_{t+1} + b_t with x_T = 0.  Padding slots must hold the
+// identity map (a = 1, b = 0).  The result overwrites b.
+
+template <typename R, int E>
+__device__ inline void scan_fwd(const R (&a)[E], R (&b)[E], int lane) {
+  R A = R(1), B = R(0);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    B = a[e] * B + b[e];
+    A = a[e] * A;
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const R pA = __shfl_up(A, d);
+    const R pB = __shfl_up(B, d);
+    if (lane >= d) {
+      B = A * pB + B;
+      A = A * pA;
+    }
+  }
+  R x = __shfl_up(B, 1);
+  if (lane == 0) x = R(0);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    x = a[e] * x + b[e];
+    b[e] = x;
+  }
+}
+
+template <typename R, int E>
+__device__ inline void scan_bwd(const R (&a)[E], R (&b)[E], int lane) {
+  R A = R(1), B = R(0);
+#pragma unroll
+  for (int e = E - 1; e >= 0; --e) {
+    B = a[e] * B + b[e];
+    A = a[e] * A;
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const R pA = __shfl_down(A, d);
+    const R pB = __shfl_down(B, d);
+    if (lane + d < kWave) {
+      B = A * pB + B;
+      A = A * pA;
+    }
+  }
+  R x = __shfl_down(B, 1);
+  if (lane == kWave - 1) x = R(0);
+#pragma unroll
+  for (int e = E - 1; e >= 0; --e) {
+    x = a[e] * x + b[e];
+    b[e] = x;
+  }
+}
+
+// Thomas factors of a tridiagonal matrix with diagonal diag(t) and constant
+// off-diagonal eo: mul_t = eo / m_{t-1}, inv_m_t = 1 / m_t for this lane's
+// slots (each lane runs the pivot recurrence up to its last slot).
+template <typename R, int E, typename Diag>
+__device__ inline void thomas_factors(int T, R eo, Diag diag, int lane, R (&mul)[E], R (&invm)[E]) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    mul[e] = R(0);
+    invm[e] = R(0);
+  }
+  const int t0 = lane * E;
+  const int tend = min(T, t0 + E);
+  R mprev = R(1);
+  for (int t = 0; t < tend; ++t) {
+    const R mu = (t == 0) ? R(0) : eo / mprev;
+    const R m = diag(t) - mu * eo;
+    if (t >= t0) {
+      mul[t - t0] = mu;
+      invm[t - t0] = R(1) / m;
+    }
+    mprev = m;
+  }
+}
+
+// Solves the tridiagonal system whose factors come from thomas_factors;
+// rhs in x on entry, solution in x on exit.
+template <typename R, int E>
+__device__ inline void thomas_solve(int T, R eo, const R (&mul)[E], const R (&invm)[E],
+                                    R (&x)[E], int lane) {
+  R a[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool ok = lane * E + e < T;
+    a[e] = ok ? -mul[e] : R(1);
+    if (!ok) x[e] = R(0);
+  }
+  scan_fwd<R, E>(a, x, lane);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const bool ok = lane * E + e < T;
+    a[e] = ok ? -eo * invm[e] : R(1);
+    x[e] = ok ? invm[e] * x[e] : R(0);
+  }
+  scan_bwd<R, E>(a, x, lane);
+}
+
+// Value of slot e's predecessor (t - 1) and successor (t + 1) in the wave.
+template <typename R, int E>
+__device__ inline R prev_slot(const R (&v)[E], int e) {
+  R up = __shfl_up(v[E - 1], 1);
+  if ((threadIdx.x & 63) == 0) up = R(0);
+  return e > 0 ? v[e > 0 ? e - 1 : 0] : up;
+}
+template <typename R, int E>
+__device__ inline R next_slot(const R (&v)[E], int e) {
+  R dn = __shfl_down(v[0], 1);
+  if ((threadIdx.x & 63) == kWave - 1) dn = R(0);
+  return e < E - 1 ? v[e < E - 1 ? e + 1 : 0] : dn;
+}
+
+// ---------------------------------------------------------------------------
+// Step 2 for time-coupled devices: inner ADMM (Appendix D) with the device
+// equalities in the x-update and the bounds split off (penalty omega).
+
+// Ramp-limited generator: min c2|p|^2 + c1'p + rho_hat/2 |p - X|^2 over
+// pmin <= p <= pmax, |p_{t+1} - p_t| <= Rl.  x-update matrix
+// (2 c2 + rho_hat + omega) I + omega D'D, tridiagonal.
+template <typename R, int E>
+__device__ void ramp_prox(const Topo& tp, R* st, int r, int g, const R (&X)[E], R rho_hat,
+                          R omega, R su, int n_inner, int lane, R (&p)[E]) {
+  const int T = tp.T;
+  const size_t nRT = size_t(tp.nR) * T;
+  R* bb = st + 0 * nRT + size_t(r) * T;
+  R* lb = st + 1 * nRT + size_t(r) * T;
+  R* br = st + 2 * nRT + size_t(r) * T;
+  R* lr = st + 3 * nRT + size_t(r) * T;
+  const R c2 = R(tp.gen_c2[g]), c1 = R(tp.gen_c1[g]), Rl = R(tp.gen_ramp[g]);
+  const R w = R(2) * c2 + rho_hat;
+  R Bb[E], Lb[E], Br[E], Lr[E], lo[E], hi[E], base[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    if (t < T) {
+      Bb[e] = bb[t];
+      Lb[e] = su * lb[t];
+      Br[e] = (t < T - 1) ? br[t] : R(0);
+      Lr[e] = (t < T - 1) ? su * lr[t] : R(0);
+      lo[e] = R(tp.gen_pmin[size_t(g) * T + t]);
+      hi[e] = R(tp.gen_pmax[size_t(g) * T + t]);
+      base[e] = rho_hat * X[e] - c1;
+    } else {
+      Bb[e] = Lb[e] = Br[e] = Lr[e] = lo[e] = hi[e] = base[e] = R(0);
+    }
+  }
+  const R eo = -omega;
+  R mul[E], invm[E];
+  thomas_factors<R, E>(T, eo, [&](int t) { return w + omega + omega * R((t > 0) + (t < T - 1)); },
+                       lane, mul, invm);
+  R x[E];
+  for (int it = 0; it < n_inner; ++it) {
+    R qr[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) qr[e] = Br[e] - Lr[e];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const R qprev = prev_slot<R, E>(qr, e);
+      x[e] = base[e] + omega * ((Bb[e] - Lb[e]) + qprev - qr[e]);
+    }
+    thomas_solve<R, E>(T, eo, mul, invm, x, lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R xn = next_slot<R, E>(x, e);
+      if (t < T) {
+        const R bnew = clampv(x[e] + Lb[e], lo[e], hi[e]);
+        Lb[e] += x[e] - bnew;
+        Bb[e] = bnew;
+      }
+      if (t < T - 1) {
+        const R dp = xn - x[e];
+        const R rnew = clampv(dp + Lr[e], -Rl, Rl);
+        Lr[e] += dp - rnew;
+        Br[e] = rnew;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    p[e] = x[e];
+    if (t < T) {
+      bb[t] = Bb[e];
+      lb[t] = Lb[e];
+      br[t] = Br[e];
+      lr[t] = Lr[e];
+    }
+  }
+}
+
+// Battery: min alpha 1'delta + rho_hat/2 |delta - c - X|^2 subject to
+// s_{t+1} = s_t + eta c_t - delta_t, s_0 = s_T = 0, and bounds on c, delta,
+// s_1..s_{T-1}.  Eliminating (c, delta) per period leaves a tridiagonal
+// system in the dynamics multipliers nu.
+template <typename R, int E>
+__device__ void battery_prox(const Topo& tp, R* st, int b, const R (&X)[E], R rho_hat, R omega,
+                             R su, int n_inner, int lane, R (&p)[E], double& obj) {
+  const int T = tp.T;
+  const size_t nBT = size_t(tp.B) * T;
+  R* arr[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) arr[q] = st + q * nBT + size_t(b) * T;
+  const R Pc = R(tp.bat_P[b]);
+  const R smax = R(tp.bat_dur[b]) * Pc;
+  const R eta = R(tp.bat_eta[b]);
+  const R alpha = R(tp.bat_alpha[b]);
+  const R det = omega * (R(2) * rho_hat + omega);
+  const R h11 = (rho_hat + omega) / det, h12 = rho_hat / det;
+  const R hgc = h11 * eta - h12, hgd = h12 * eta - h11;  // H^-1 g, g = (eta, -1)
+  const R kappa = eta * hgc - hgd;                         // g' H^-1 g
+  const R iw = R(1) / omega;
+  R Bc[E], Lc[E], Bd[E], Ld[E], Bs[E], Ls[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    const bool ok = t < T, oks = t >= 1 && t < T;
+    Bc[e] = ok ? arr[0][t] : R(0);
+    Lc[e] = ok ? su * arr[1][t] : R(0);
+    Bd[e] = ok ? arr[2][t] : R(0);
+    Ld[e] = ok ? su * arr[3][t] : R(0);
+    Bs[e] = oks ? arr[4][t] : R(0);
+    Ls[e] = oks ? su * arr[5][t] : R(0);
+  }
+  R mul[E], invm[E];
+  const R eo = -iw;
+  thomas_factors<R, E>(T, eo, [&](int t) { return kappa + iw * R((t < T - 1) + (t > 0)); }, lane,
+                       mul, invm);
+  R c[E], dl[E];
+  for (int it = 0; it < n_inner; ++it) {
+    R qs[E], nu[E], hrc[E], hrd[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) qs[e] = Bs[e] - Ls[e];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R rc = omega * (Bc[e] - Lc[e]) - rho_hat * X[e];
+      const R rd = omega * (Bd[e] - Ld[e]) + rho_hat * X[e] - alpha;
+      hrc[e] = h11 * rc + h12 * rd;
+      hrd[e] = h12 * rc + h11 * rd;
+      const R qn = next_slot<R, E>(qs, e);
+      nu[e] = (t < T - 1 ? qn : R(0)) - qs[e] - (eta * hrc[e] - hrd[e]);
+    }
+    thomas_solve<R, E>(T, eo, mul, invm, nu, lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R np = prev_slot<R, E>(nu, e);
+      c[e] = hrc[e] + nu[e] * hgc;
+      dl[e] = hrd[e] + nu[e] * hgd;
+      if (t < T) {
+        R nb = clampv(c[e] + Lc[e], R(0), Pc);
+        Lc[e] += c[e] - nb;
+        Bc[e] = nb;
+        nb = clampv(dl[e] + Ld[e], R(0), Pc);
+        Ld[e] += dl[e] - nb;
+        Bd[e] = nb;
+      }
+      if (t >= 1 && t < T) {
+        const R s = qs[e] + (nu[e] - np) * iw;
+        const R nb = clampv(s + Ls[e], R(0), smax);
+        Ls[e] += s - nb;
+        Bs[e] = nb;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    p[e] = dl[e] - c[e];
+    if (t < T) {
+      obj += double(alpha) * double(dl[e]);
+      arr[0][t] = Bc[e];
+      arr[1][t] = Lc[e];
+      arr[2][t] = Bd[e];
+      arr[3][t] = Ld[e];
+      if (t >= 1) {
+        arr[4][t] = Bs[e];
+        arr[5][t] = Ls[e];
+      }
+    }
+  }
+}
+
+// Step 2 for one generator, load or battery (one wavefront, all periods):
+// deferred phase-dual update, theta = avg_k(thetabar - v), then the prox of
+// power at target p - avg_k(pbar + u) with penalty (K+1) rho_p.
+template <typename R, typename VT, int E>
+__device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R rho_hat,
+                          double& acc_dp, double& acc_obj) {
+  const Topo& tp = a.tp;
+  const int T = tp.T;
+  const int n = tp.nc_node[j];
+  R X[E], pold[E], pn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    X[e] = pold[e] = pn[e] = R(0);
+    if (t < T) {
+      const size_t o = size_t(j) * T + t;
+      const R po = a.st.pnc[o], tho = a.st.thnc[o];
+      const R aw = a.st.avgW[size_t(n) * T + t], at = a.st.avgTB[size_t(n) * T + t];
+      const R vb = sv * (a.st.vbar[o] + tho - at);
+      a.st.vbar[o] = vb;
+      a.st.thnc[o] = at - vb;
+      X[e] = po - aw;
+      pold[e] = po;
+    }
+  }
+  const R omega = R(a.g.omega_scale) * rho_hat;
+  double obj = 0.0;
+  if (j < tp.G) {
+    const int r = tp.ramp_idx[j];
+    const R c2 = R(tp.gen_c2[j]), c1 = R(tp.gen_c1[j]);
+    if (r < 0) {
+      const R den = R(2) * c2 + rho_hat;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int t = lane * E + e;
+        if (t < T)
+          pn[e] = clampv((rho_hat * X[e] - c1) / den, R(tp.gen_pmin[size_t(j) * T + t]),
+                         R(tp.gen_pmax[size_t(j) * T + t]));
+      }
+    } else {
+      ramp_prox<R, E>(tp, a.st.ramp_st, r, j, X, rho_hat, omega, su, a.g.inner_iters, lane, pn);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (lane * E + e < T) obj += double(c2) * double(pn[e]) * double(pn[e]) + double(c1) * double(pn[e]);
+  } else if (j < tp.G + tp.D) {
+    const int d = j - tp.G;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      if (t < T) pn[e] = -R(tp.load_d[size_t(d) * T + t]);
+    }
+  } else {
+    battery_prox<R, E>(tp, a.st.bat_st, j - tp.G - tp.D, X, rho_hat, omega, su, a.g.inner_iters,
+                       lane, pn, obj);
+  }
+  double dp = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    if (t < T) {
+      a.st.pnc[size_t(j) * T + t] = pn[e];
+      const double d = double(pn[e]) - double(pold[e]);
+      dp += d * d;
+    }
+  }
+  acc_dp += double(tp.Kp) * dp;
+  acc_obj += obj;
+}
+
+// Step 1 for one line and one 16-byte vector of contingencies (Section 4.2,
+// AC line prox with the per-contingency susceptance and capacity of the N-1
+// model), preceded by the deferred scaled-price update v += theta - thetabar
+// of the previous iteration and the pending penalty rescale.  Both end
+// nodes of a line call this with identical inputs.
+template <typename R, int VEC>
+struct LineOut {
+  R p[VEC], tm[VEC], v1[VEC], v2[VEC], half[VEC];
+};
+
+template <typename R, typename VT, int VEC>
+__device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC>& Tm,
+                                          const Vec<VT, VEC>& V1, const Vec<VT, VEC>& V2,
+                                          const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
+                                          const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
+                                          const Vec<int32_t, VEC>& ok, int l, const R* td_old,
+                                          int k0, int Kp, R s, R cap, R rp, R rt, R sv,
+                                          LineOut<R, VEC>& o) {
+  const R inv2s = R(0.5) / s;
+  const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;  // 2 rho_p + rho_th / (2 s^2)
+  const R ca = rp / den;                                // weight of z2 - z1
+  const R cb = rt * inv2s / den;                        // weight of xi1 - xi2
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const bool outg = ok.x[e] == l;
+    const R half = outg ? td_old[e] : P.x[e] * inv2s;
+    const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
+    R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
+    R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
+    const R z1 = -P.x[e] - Wf.x[e];  // ptilde - u at terminal 1 (p1 = -P)
+    const R z2 = P.x[e] - Wh.x[e];   // ptilde - u at terminal 2
+    const R xi1 = Bf.x[e] - v1, xi2 = Bh.x[e] - v2;
+    R tm = R(0.5) * (xi1 + xi2);
+    R pn, hn;
+    if (outg) {
+      pn = R(0);
+      hn = R(0.5) * (xi1 - xi2);
+    } else {
+      pn = clampv(ca * (z2 - z1) + cb * (xi1 - xi2), -cap, cap);
+      hn = pn * inv2s;
+    }
+    if (k0 + e >= Kp) pn = tm = v1 = v2 = hn = R(0);
+    o.p[e] = pn;
+    o.tm[e] = tm;
+    o.v1[e] = v1;
+    o.v2[e] = v2;
+    o.half[e] = hn;
+  }
+}
+
+// Steps 1 and 3 for one (period, node) row and one 16-byte vector of
+// contingencies.  acc: FP64 residual partials [sum |n| pbar^2, sum theta
+// tilde^2, sum |n| dpbar^2, sum |n| dthetabar^2, sum over lines of 2 dP^2].
+template <typename R, typename VT>
+__device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, const Buf<R, VT>& B,
+                                 int row, int v, int q0, int q1, bool check, R rp, R rt, R sv,
+                                 double (&acc)[5], R& sumw, R& sumb) {
+  constexpr int VEC = 16 / sizeof(R);
+  using VR = Vec<R, VEC>;
+  using VV = Vec<VT, VEC>;
+  using VI = Vec<int32_t, VEC>;
+  const Topo& tp = a.tp;
+  const int T = tp.T;
+  const int t = row / tp.N, n = row - t * tp.N;  // row = t * N + n
+  const int k0 = v * VEC;
+  const size_t off = size_t(row) * tp.Kpp + k0;
+  const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+  const VR Uo = ld_stream(reinterpret_cast<const VR*>(A.U + off));
+  const VR Wo = *reinterpret_cast<const VR*>(A.W + off);
+  const VR Bo = *reinterpret_cast<const VR*>(A.TB + off);
+  const R* td_old = A.Td + size_t(t) * tp.Kpp + k0;
+  R* td_new = B.Td + size_t(t) * tp.Kpp + k0;
+  // theta sums shifted by the node's first terminal phase c (for the
+  // theta-tilde norm without cancellation)
+  R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) sp[e] = sb[e] = c[e] = s1[e] = s2[e] = R(0);
+  bool first = true;
+  const size_t lrow = size_t(t) * tp.L, nrow = size_t(t) * tp.N;
+  constexpr int NB = OPF_SWEEP_BATCH;
+  for (int q = q0; q < q1; q += NB) {
+    int2 term[NB];
+    VR P[NB], Tm[NB], Wx[NB], Bx[NB];
+    VV V1[NB], V2[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) term[u] = (q + u < q1) ? tp.node_lterm[q + u] : make_int2(-1, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (term[u].x >= 0) {
+        const size_t ol = (lrow + (term[u].x >> 1)) * tp.Kpp + k0;
+        const size_t oo = (nrow + term[u].y) * tp.Kpp + k0;
+        P[u] = *reinterpret_cast<const VR*>(A.P + ol);
+        Tm[u] = *reinterpret_cast<const VR*>(A.Tm + ol);
+        V1[u] = *reinterpret_cast<const VV*>(A.V1 + ol);
+        V2[u] = *reinterpret_cast<const VV*>(A.V2 + ol);
+        Wx[u] = *reinterpret_cast<const VR*>(A.W + oo);
+        Bx[u] = *reinterpret_cast<const VR*>(A.TB + oo);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (term[u].x < 0) break;
+      const int l = term[u].x >> 1;
+      const bool to_end = term[u].x & 1;  // this node is the line's terminal-2 node
+      const size_t ol = (lrow + l) * tp.Kpp + k0;
+      LineOut<R, VEC> o;
+      line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo, to_end ? Wo : Wx[u],
+                            to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l, td_old, k0, tp.Kp,
+                            R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+      if (!to_end) {  // the from node stores the line's new state
+        VR Pn, Tn;
+        VV V1n, V2n;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          Pn.x[e] = o.p[e];
+          Tn.x[e] = o.tm[e];
+          V1n.x[e] = DIO<VT, R>::out(o.v1[e]);
+          V2n.x[e] = DIO<VT, R>::out(o.v2[e]);
+          if (ok.x[e] == l) td_new[e] = o.half[e];
+          if (check) {
+            const double dp = double(o.p[e]) - double(P[u].x[e]);
+            acc[4] += 2.0 * dp * dp;
+          }
+        }
+        st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
+        st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
+        st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
+        st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const R pj = to_end ? o.p[e] : -o.p[e];
+        const R thj = to_end ? o.tm[e] - o.half[e] : o.tm[e] + o.half[e];
+        sp[e] += pj;
+        sb[e] += thj;
+        if (first) c[e] = thj;
+        const R d = thj - c[e];
+        s1[e] += d;
+        s2[e] += d * d;
+      }
+      first = false;
+    }
+  }
+  // generators, loads, batteries: their new schedules come from k_devices
+  const int r0 = tp.node_nptr[n], r1 = tp.node_nptr[n + 1];
+  for (int q = r0; q < r1; ++q) {
+    const int j = tp.node_nterm[q];
+    const R pj = a.st.pnc[size_t(j) * T + t];
+    const R thj = a.st.thnc[size_t(j) * T + t];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      sp[e] += pj;
+      sb[e] += thj;
+      if (first) c[e] = thj;
+      const R d = thj - c[e];
+      s1[e] += d;
+      s2[e] += d * d;
+    }
+    first = false;
+  }
+  const double dg = tp.deg[n];
+  const R rdg = R(dg);
+  VR Un, Wn, Bn;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const bool valid = k0 + e < tp.Kp;
+    const R pb = sp[e] / rdg;
+    const R tb = sb[e] / rdg;
+    const R un = Uo.x[e] + pb;
+    const R wn = un + pb;
+    if (check && valid) {
+      const double dpb = double(pb);
+      acc[0] += dg * dpb * dpb;
+      acc[1] += fmax(double(s2[e]) - double(s1[e]) * double(s1[e]) / dg, 0.0);
+      const double dd = dpb - double(Wo.x[e] - Uo.x[e]);
+      acc[2] += dg * dd * dd;
+      const double dt = double(tb) - double(Bo.x[e]);
+      acc[3] += dg * dt * dt;
+    }
+    Un.x[e] = valid ? un : R(0);
+    Wn.x[e] = valid ? wn : R(0);
+    Bn.x[e] = valid ? tb : R(0);
+    sumw += Wn.x[e];
+    sumb += Bn.x[e];
+  }
+  st_stream(reinterpret_cast<VR*>(B.U + off), Un);
+  st_stream(reinterpret_cast<VR*>(B.W + off), Wn);
+  st_stream(reinterpret_cast<VR*>(B.TB + off), Bn);
+}
+
+// Rows (period, node) map onto lane groups of lanes_per_row lanes (a power
+// of two, at most one wavefront); each lane takes the row's 16-byte vectors
+// q, q + lanes_per_row, ...  The contingency sums of a row are reduced with
+// shuffles inside its lane group (no LDS, no barrier).
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a) {
+  Ctl* ctl = a.g.ctl;
+  if (ctl->done) return;
+  const int cur = ctl->cur;
+  const Buf<R, VT> A = a.st.buf[cur];
+  const Buf<R, VT> B = a.st.buf[cur ^ 1];
+  const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
+  const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
+  __shared__ double sh[kBlock / kWave];
+  const int lb = blockIdx.x;
+  const Sweep sweep = xcd_sweep(lb, gridDim.x, a.g.n_grps);
+  const int nv = a.g.nv, lpr = a.g.lanes_per_row;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int rw = lane / lpr, q = lane - rw * lpr;
+  const int rows_per_wave = kWave / lpr;
+  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
+    const int64_t row = (gi * (kBlock / kWave) + w) * rows_per_wave + rw;
+    const bool act = row < NT;
+    R sumw = R(0), sumb = R(0);
+    if (act) {
+      const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
+      const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
+      for (int v = q; v < nv; v += lpr)
+        sweep_vec<R, VT>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+    }
+    for (int d = lpr >> 1; d > 0; d >>= 1) {
+      sumw += __shfl_xor(sumw, d);
+      sumb += __shfl_xor(sumb, d);
+    }
+    if (act && q == 0) {
+      const int t = int(row / a.tp.N), n = int(row - int64_t(t) * a.tp.N);
+      a.st.avgW[size_t(n) * a.tp.T + t] = sumw / R(a.tp.Kp);
+      a.st.avgTB[size_t(n) * a.tp.T + t] = sumb / R(a.tp.Kp);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double s = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) a.g.part_sweep[5 * lb + k] = s;
+  }
+}
+
+// Step 2 for all generators, loads and batteries, one per wavefront.
+template <typename R, typename VT, int E>
+__global__ void __launch_bounds__(kBlock) k_devices(KArgs<R, VT> a) {
+  Ctl* ctl = a.g.ctl;
+  if (ctl->done) return;
+  const R rp = R(ctl->rho_p), su = R(ctl->su), sv = R(ctl->sv);
+  __shared__ double sh[kBlock / kWave];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (kBlock / kWave) + w;
+  double dp = 0.0, ob = 0.0;
+  if (j < a.tp.Jnc) nc_device<R, VT, E>(a, j, lane, su, sv, R(a.tp.Kp) * rp, dp, ob);
+  dp = block_sum(dp, sh);
+  ob = block_sum(ob, sh);
+  if (threadIdx.x == 0) {
+    a.g.part_nc[2 * blockIdx.x] = dp;
+    a.g.part_nc[2 * blockIdx.x + 1] = ob;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual norms, stopping test and adaptive penalty (single block).
+__device__ inline double adapt_rule(double rho, double rpri, double rdual, double mu, double gamma) {
+  if (rpri > mu * rdual) return rho * gamma;
+  if (rdual > mu * rpri) return rho / gamma;
+  return rho;
+}
+
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
+  Ctl* ctl = a.g.ctl;
+  __shared__ double sh[kBlock / kWave];
+  __shared__ int sdone;
+  if (threadIdx.x == 0) sdone = ctl->done;
+  __syncthreads();
+  if (sdone) {
+    if (threadIdx.x == 0) ctl->launches += 1;
+    return;
+  }
+  const int iter = ctl->iter + 1;
+  const bool check = (iter % ctl->check_every) == 0;
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};  // 5 sweep partials, device dual, objective
+  if (check) {
+    for (int i = threadIdx.x; i < a.g.n_sweep_blocks; i += kBlock)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s[k] += a.g.part_sweep[5 * i + k];
+    for (int i = threadIdx.x; i < a.g.n_nc_blocks; i += kBlock) {
+      s[5] += a.g.part_nc[2 * i];
+      s[6] += a.g.part_nc[2 * i + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) s[k] = block_sum(s[k], sh);
+  }
+  if (threadIdx.x != 0) return;
+  const double rp = ctl->rho_p, rt = ctl->rho_th;
+  double su = 1.0, sv = 1.0;
+  int conv = 0, bad = 0;
+  if (check) {
+    // ||ptilde' - ptilde||^2 = sum over terminal copies of dp^2 - sum |n| dpbar^2
+    const double pp = fmax(s[0], 0.0), pt = fmax(s[1], 0.0);
+    const double dp = rp * rp * fmax(s[4] + s[5] - s[2], 0.0);
+    const double dt = rt * rt * fmax(s[3], 0.0);
+    Rec rec;
+    rec.primal_p = sqrt(pp);
+    rec.primal_th = sqrt(pt);
+    rec.dual_p = sqrt(dp);
+    rec.dual_th = sqrt(dt);
+    rec.rms_primal = sqrt(pp + pt) / ctl->rms_norm;
+    rec.rms_dual = sqrt(dp + dt) / ctl->rms_norm;
+    rec.threshold = ctl->eps_eff;
+    rec.objective = s[6];
+    rec.rho_p = rp;
+    rec.rho_th = rt;
+    rec.iter = iter;
+    rec.precision = ctl->precision;
+    bad = !(isfinite(rec.rms_primal) && isfinite(rec.rms_dual));
+    conv = !bad && fmax(rec.rms_primal, rec.rms_dual) <= ctl->eps_eff && iter >= ctl->min_iter;
+    rec.converged = conv;
+    if (ctl->adapt_every > 0 && iter % ctl->adapt_every == 0 && !bad) {
+      const double np = adapt_rule(rp, rec.primal_p, rec.dual_p, ctl->mu, ctl->gamma);
+      const double nt = adapt_rule(rt, rec.primal_th, rec.dual_th, ctl->mu, ctl->gamma);
+      su = rp / np;
+      sv = rt / nt;
+      ctl->rho_p = np;
+      ctl->rho_th = nt;
+    }
+    a.g.ring[(iter - 1) % kRing] = rec;
+  }
+  ctl->su = su;
+  ctl->sv = sv;
+  ctl->launches += 1;
+  ctl->scale_iter = ctl->launches;
+  ctl->iter = iter;
+  ctl->cur ^= 1;  // the sweep wrote the other buffer
+  if (conv) ctl->converged = 1;
+  if (bad) ctl->numeric_bad = 1;
+  if (conv || bad || iter >= ctl->max_iter) ctl->done = 1;
+}
+
+// u <- su u after a penalty change (current buffer, same row mapping as the
+// sweep).
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_rescale(KArgs<R, VT> a) {
+  constexpr int VEC = 16 / sizeof(R);
+  using VR = Vec<R, VEC>;
+  Ctl* ctl = a.g.ctl;
+  if (ctl->scale_iter != ctl->launches) return;
+  const R su = R(ctl->su);
+  if (su == R(1)) return;
+  const Buf<R, VT> C = a.st.buf[ctl->cur];
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, a.g.n_grps);
+  const int nv = a.g.nv, lpr = a.g.lanes_per_row;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int rw = lane / lpr, q = lane - rw * lpr;
+  const int rows_per_wave = kWave / lpr;
+  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
+    const int64_t row = (gi * (kBlock / kWave) + w) * rows_per_wave + rw;
+    const bool act = row < NT;
+    R sumw = R(0);
+    if (act) {
+      for (int v = q; v < nv; v += lpr) {
+        const size_t off = size_t(row) * a.tp.Kpp + v * VEC;
+        const VR U = *reinterpret_cast<const VR*>(C.U + off);
+        const VR W = *reinterpret_cast<const VR*>(C.W + off);
+        VR Un, Wn;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          Un.x[e] = su * U.x[e];
+          Wn.x[e] = W.x[e] + (su - R(1)) * U.x[e];
+          sumw += Wn.x[e];
+        }
+        *reinterpret_cast<VR*>(C.U + off) = Un;
+        *reinterpret_cast<VR*>(C.W + off) = Wn;
+      }
+    }
+    for (int d = lpr >> 1; d > 0; d >>= 1) sumw += __shfl_xor(sumw, d);
+    if (act && q == 0) {
+      const int t = int(row / a.tp.N), n = int(row - int64_t(t) * a.tp.N);
+      a.st.avgW[size_t(n) * a.tp.T + t] = sumw / R(a.tp.Kp);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Export of one field of the iterate in the paper's layout, as FP64.
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, double* dst,
+                                                   int64_t count) {
+  const Topo& tp = a.tp;
+  const double sv = a.g.ctl->sv;
+  const Buf<R, VT> C = a.st.buf[a.g.ctl->cur];
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const int T = tp.T;
+  if (field <= 4) {  // [Kp][L][T]
+    const int t = int(i % T);
+    const int l = int((i / T) % tp.L);
+    const int k = int(i / (int64_t(T) * tp.L));
+    const size_t o = (size_t(t) * tp.L + l) * tp.Kpp + k;
+    const double P = double(C.P[o]);
+    if (field == 0) {
+      dst[i] = P;
+      return;
+    }
+    const bool outg = tp.outage_k[k] == l;
+    const double half = outg ? double(C.Td[size_t(t) * tp.Kpp + k]) : P * (0.5 / tp.sus[l]);
+    const double th1 = double(C.Tm[o]) + half, th2 = double(C.Tm[o]) - half;
+    if (field == 1) dst[i] = th1;
+    if (field == 2) dst[i] = th2;
+    if (field == 3 || field == 4) {
+      const int nd = field == 3 ? tp.line_from[l] : tp.line_to[l];
+      const double tb = double(C.TB[(size_t(t) * tp.N + nd) * tp.Kpp + k]);
+      const double vs = double(DIO<VT, R>::in(field == 3 ? C.V1[o] : C.V2[o]));
+      dst[i] = sv * (vs + (field == 3 ? th1 : th2) - tb);
+    }
+    return;
+  }
+  if (field <= 7) {  // [Kp][N][T]
+    const int t = int(i % T);
+    const int n = int((i / T) % tp.N);
+    const int k = int(i / (int64_t(T) * tp.N));
+    const size_t o = (size_t(t) * tp.N + n) * tp.Kpp + k;
+    if (field == 5) dst[i] = double(C.U[o]);
+    if (field == 6) dst[i] = double(C.W[o]) - double(C.U[o]);
+    if (field == 7) dst[i] = double(C.TB[o]);
+    return;
+  }
+  // [Jnc][T]
+  const int t = int(i % T);
+  const int j = int(i / T);
+  if (field == 8) dst[i] = double(a.st.pnc[i]);
+  if (field == 9) dst[i] = double(a.st.thnc[i]);
+  if (field == 10) {
+    const int n = tp.nc_node[j];
+    dst[i] = sv * (double(a.st.vbar[i]) + double(a.st.thnc[i]) - double(a.st.avgTB[size_t(n) * T + t]));
+  }
+}
+
+// Widening copy (FP32 iterate -> FP64 iterate); same element layout.
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock) k_widen(const S* src, D* dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) dst[i] = D(DIO<S, float>::in(src[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+template <typename R, typename VT>
+void launch_devices(const KArgs<R, VT>& a, hipStream_t s) {
+  if (a.g.n_nc_blocks == 0) return;
+  const int E = (a.tp.T + kWave - 1) / kWave;
+  switch (E) {
+    case 1: k_devices<R, VT, 1><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
+    case 2: k_devices<R, VT, 2><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
+    case 3: k_devices<R, VT, 3><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
+    default: k_devices<R, VT, 4><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
+  }
+}
+
+// Blocks of k_sweep that are resident at once on the current device: the
+// sweep grid is sized to this so that all blocks advance as one front.
+template <typename R, typename VT>
+int sweep_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<R, VT>, kBlock, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+template <typename R, typename VT>
+void launch_sweep(const KArgs<R, VT>& a, hipStream_t s) {
+  k_sweep<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+}
+
+template <typename R, typename VT>
+void launch_finalize(const KArgs<R, VT>& a, hipStream_t s) {
+  k_finalize<R, VT><<<1, kBlock, 0, s>>>(a);
+}
+
+template <typename R, typename VT>
+void launch_rescale(const KArgs<R, VT>& a, hipStream_t s) {
+  k_rescale<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+}
+
+template <typename R, typename VT>
+void launch_export(const KArgs<R, VT>& a, int field, double* dst, hipStream_t s) {
+  int64_t count;
+  const int64_t KT = int64_t(a.tp.Kp) * a.tp.T;
+  if (field <= 4)
+    count = KT * a.tp.L;
+  else if (field <= 7)
+    count = KT * a.tp.N;
+  else
+    count = int64_t(a.tp.Jnc) * a.tp.T;
+  if (count == 0) return;
+  const int64_t grid = (count + kBlock - 1) / kBlock;
+  k_export<R, VT><<<dim3(unsigned(grid)), kBlock, 0, s>>>(a, field, dst, count);
+}
+
+template <typename S, typename D>
+static void widen(const S* src, D* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_widen<S, D><<<dim3(unsigned((n + kBlock - 1) / kBlock)), kBlock, 0, s>>>(src, dst, n);
+}
+
+template <typename VT>
+void launch_widen(const KArgs<float, VT>& a, const KArgs<double, double>& b, hipStream_t s) {
+  const Topo& tp = a.tp;
+  const int64_t line = int64_t(tp.L) * tp.T * tp.Kpp;
+  const int64_t node = int64_t(tp.N) * tp.T * tp.Kpp;
+  for (int i = 0; i < 2; ++i) {
+    const Buf<float, VT>& x = a.st.buf[i];
+    const Buf<double, double>& y = b.st.buf[i];
+    widen(x.P, y.P, line, s);
+    widen(x.Tm, y.Tm, line, s);
+    widen(x.V1, y.V1, line, s);
+    widen(x.V2, y.V2, line, s);
+    widen(x.Td, y.Td, int64_t(tp.T) * tp.Kpp, s);
+    widen(x.U, y.U, node, s);
+    widen(x.W, y.W, node, s);
+    widen(x.TB, y.TB, node, s);
+  }
+  widen(a.st.avgW, b.st.avgW, int64_t(tp.N) * tp.T, s);
+  widen(a.st.avgTB, b.st.avgTB, int64_t(tp.N) * tp.T, s);
+  const int64_t nc = int64_t(tp.Jnc) * tp.T;
+  widen(a.st.pnc, b.st.pnc, nc, s);
+  widen(a.st.thnc, b.st.thnc, nc, s);
+  widen(a.st.vbar, b.st.vbar, nc, s);
+  widen(a.st.ramp_st, b.st.ramp_st, 4 * int64_t(tp.nR) * tp.T, s);
+  widen(a.st.bat_st, b.st.bat_st, 6 * int64_t(tp.B) * tp.T, s);
+}
+
+#define OPF_INSTANTIATE(R, VT)                                                       \
+  template int sweep_resident_blocks<R, VT>();                                       \
+  template void launch_devices<R, VT>(const KArgs<R, VT>&, hipStream_t);            \
+  template void launch_sweep<R, VT>(const KArgs<R, VT>&, hipStream_t);              \
+  template void launch_finalize<R, VT>(const KArgs<R, VT>&, hipStream_t);           \
+  template void launch_rescale<R, VT>(const KArgs<R, VT>&, hipStream_t);            \
+  template void launch_export<R, VT>(const KArgs<R, VT>&, int, double*, hipStream_t);
+
+OPF_INSTANTIATE(double, double)
+OPF_INSTANTIATE(float, float)
+OPF_INSTANTIATE(float, bf16_t)
+template void launch_widen<float>(const KArgs<float, float>&, const KArgs<double, double>&, hipStream_t);
+template void launch_widen<bf16_t>(const KArgs<float, bf16_t>&, const KArgs<double, double>&, hipStream_t);
+
+}  // namespace opf
