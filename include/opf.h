@@ -137,21 +137,43 @@ opf_status opf_workspace_size(opf_ctx* ctx, const opf_network* net, size_t* byte
 opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
                             void* d_workspace, size_t bytes);
 
+/* Batched form (several independent instances of uneven size in one context;
+ * the paper batches scenarios in Section 5.5): the workspace holds all of
+ * them and every phase of an iteration is one launch over a work list
+ * spanning all instances.  Each instance keeps its own penalties, counters
+ * and convergence flag; converged instances are skipped.  FP64 polishing is
+ * not applied to batches.  Instance indices follow the order of nets. */
+opf_status opf_workspace_size_batch(opf_ctx* ctx, const opf_network* nets, int32_t count,
+                                    size_t* bytes);
+opf_status opf_load_batch(opf_ctx* ctx, const opf_network* nets, int32_t count,
+                          void* d_workspace, size_t bytes);
+
+/* Number of loaded instances (0 before a load). */
+opf_status opf_num_instances(opf_ctx* ctx, int32_t* count);
+
+/* Resets every instance to the all-zero start and the initial penalties. */
+opf_status opf_reset(opf_ctx* ctx);
+
 /* Enqueues n_iters message-passing iterations (Section 3.2 steps 1-3 plus
  * residuals and the adaptive penalty).  Asynchronous.  Iterations after
  * convergence or max_iter are skipped on the device. */
 opf_status opf_iterate(opf_ctx* ctx, int32_t n_iters);
 
-/* Iterates until eq. converge holds or max_iter; synchronises.  Returns
- * OPF_OK or OPF_NOT_CONVERGED and the last residual record in *out. */
+/* Iterates until eq. converge holds (for every instance) or max_iter;
+ * synchronises.  Returns OPF_OK or OPF_NOT_CONVERGED and instance 0's last
+ * residual record in *out. */
 opf_status opf_solve(opf_ctx* ctx, opf_resid* out);
 
-/* Synchronises the stream and returns the last residual record. */
+/* Synchronises the stream and returns the last residual record (of
+ * instance 0, or of instance i for the _i form). */
 opf_status opf_residuals(opf_ctx* ctx, opf_resid* out);
+opf_status opf_residuals_i(opf_ctx* ctx, int32_t instance, opf_resid* out);
 
 /* Copies up to max records of the residual history (oldest first, at most
  * the last 4096 iterations) into out; *n receives the count.  Synchronises. */
 opf_status opf_residual_history(opf_ctx* ctx, opf_resid* out, int32_t max, int32_t* n);
+opf_status opf_residual_history_i(opf_ctx* ctx, int32_t instance, opf_resid* out, int32_t max,
+                                  int32_t* n);
 
 /* Fields of the iterate in the paper's layout (Section 4.1), FP64. */
 typedef enum {
@@ -168,12 +190,15 @@ typedef enum {
   OPF_FIELD_VNC = 10    /* their phase duals averaged over k [G+D+B][T] */
 } opf_field;
 
-/* Number of doubles in a field. */
+/* Number of doubles in a field (of instance 0, or of instance i). */
 opf_status opf_field_size(opf_ctx* ctx, int32_t field, size_t* count);
+opf_status opf_field_size_i(opf_ctx* ctx, int32_t instance, int32_t field, size_t* count);
 
 /* Writes one field of the current iterate, as FP64 in the layout above,
  * to the device buffer d_dst (count doubles).  Enqueued on the stream. */
 opf_status opf_get_field(opf_ctx* ctx, int32_t field, double* d_dst, size_t count);
+opf_status opf_get_field_i(opf_ctx* ctx, int32_t instance, int32_t field, double* d_dst,
+                           size_t count);
 
 /* Enables (1) or disables (0) per-kernel HIP-event timing of subsequent
  * opf_iterate calls; enabling clears the accumulated times. */
@@ -196,6 +221,22 @@ opf_status opf_kernel_times(opf_ctx* ctx, double* ms, int64_t* launches);
 /* Algorithmic device bytes one launch of a kernel class moves for the
  * loaded network and current precision (used for roofline reporting). */
 opf_status opf_kernel_bytes(opf_ctx* ctx, int32_t kernel, double* bytes);
+
+/* Launch configuration chosen by opf_autotune. */
+typedef struct {
+  int32_t lanes_shift;   /* lanes per (period, node) row: natural count << shift */
+  double grid_factor;    /* sweep grid as a multiple of the resident blocks     */
+  double ms_per_iter;    /* measured time of one iteration with this choice     */
+  int32_t from_cache;    /* 1 if read from cache_path instead of measured       */
+} opf_tuning;
+
+/* Times `trials` iterations for each candidate launch configuration of the
+ * loaded instance(s) (lanes per row halved/natural/doubled x sweep grid 0.5/1/2
+ * times the resident blocks), keeps the fastest, and resets the iterate to
+ * the zero start.  With cache_path non-NULL, a result for the same device,
+ * precision and instance shape is read from that text file instead of being
+ * measured, and new results are appended to it.  Synchronises. */
+opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, opf_tuning* out);
 
 /* Text of the last failure on ctx (or of opf_create when ctx is NULL). */
 const char* opf_last_error(opf_ctx* ctx);

@@ -76,6 +76,11 @@ class Resid(Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Tuning(Structure):
+    _fields_ = [("lanes_shift", c_int32), ("grid_factor", c_double),
+                ("ms_per_iter", c_double), ("from_cache", c_int32)]
+
+
 class OpfError(RuntimeError):
     pass
 
@@ -106,6 +111,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "opf_set_timing": (c_int32, [P, c_int32]),
         "opf_kernel_times": (c_int32, [P, POINTER(c_double), POINTER(c_int64)]),
         "opf_kernel_bytes": (c_int32, [P, c_int32, POINTER(c_double)]),
+        "opf_workspace_size_batch": (c_int32, [P, POINTER(Network), c_int32, POINTER(c_size_t)]),
+        "opf_load_batch": (c_int32, [P, POINTER(Network), c_int32, c_void_p, c_size_t]),
+        "opf_num_instances": (c_int32, [P, POINTER(c_int32)]),
+        "opf_reset": (c_int32, [P]),
+        "opf_residuals_i": (c_int32, [P, c_int32, POINTER(Resid)]),
+        "opf_residual_history_i": (c_int32, [P, c_int32, POINTER(Resid), c_int32, POINTER(c_int32)]),
+        "opf_field_size_i": (c_int32, [P, c_int32, c_int32, POINTER(c_size_t)]),
+        "opf_get_field_i": (c_int32, [P, c_int32, c_int32, c_void_p, c_size_t]),
+        "opf_autotune": (c_int32, [P, c_int32, c_char_p, POINTER(Tuning)]),
         "opf_last_error": (c_char_p, [P]),
         "opf_destroy": (None, [P]),
     }
@@ -180,10 +194,12 @@ def _options(dtype: str, dual_dtype: Optional[str], stream_ptr: int, **kw) -> Op
 
 
 class Solver:
-    """One instance loaded on one GPU.
+    """One instance, or a batch of instances, loaded on one GPU.
 
-    dtype: 'f64' or 'f32' iterate; dual_dtype 'bf16' stores the line phase
-    duals in BF16 (with dtype 'f32').  Keyword options map onto opf_options.
+    inst: one network, or a list of networks (a batch: every phase of an
+    iteration is one launch over all of them).  dtype: 'f64' or 'f32'
+    iterate; dual_dtype 'bf16' stores the line phase duals in BF16 (with
+    dtype 'f32').  Keyword options map onto opf_options.
     """
 
     def __init__(self, inst, dtype: str = "f64", dual_dtype: Optional[str] = None,
@@ -199,16 +215,21 @@ class Solver:
         ctx = c_void_p()
         self._check(self.lib.opf_create(byref(self.opt), byref(ctx)), None)
         self.ctx = ctx
-        arrays = NetworkArrays(inst)
+        insts = list(inst) if isinstance(inst, (list, tuple)) else [inst]
+        self.insts = insts
+        arrays = [NetworkArrays(x) for x in insts]
+        nets = (Network * len(insts))(*[a.net for a in arrays])
         nbytes = c_size_t()
-        self._check(self.lib.opf_workspace_size(self.ctx, byref(arrays.net), byref(nbytes)))
+        self._check(self.lib.opf_workspace_size_batch(self.ctx, nets, len(insts), byref(nbytes)))
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        self._check(self.lib.opf_load_network(self.ctx, byref(arrays.net),
-                                              c_void_p(self.ws.data_ptr()), nbytes))
-        self.N, self.T, self.K = int(inst.N), int(inst.T), int(inst.K)
-        self.L = len(inst.line_from)
-        self.Jnc = len(inst.gen_node) + len(inst.load_node) + len(inst.bat_node)
+        self._check(self.lib.opf_load_batch(self.ctx, nets, len(insts),
+                                            c_void_p(self.ws.data_ptr()), nbytes))
         self.workspace_bytes = int(nbytes.value)
+        self.shapes = [dict(N=int(x.N), T=int(x.T), K=int(x.K), L=len(x.line_from),
+                            Jnc=len(x.gen_node) + len(x.load_node) + len(x.bat_node))
+                       for x in insts]
+        s0 = self.shapes[0]
+        self.N, self.T, self.K, self.L, self.Jnc = s0["N"], s0["T"], s0["K"], s0["L"], s0["Jnc"]
 
     # -- helpers ---------------------------------------------------------------
     def _check(self, st, ctx="self"):
@@ -229,6 +250,10 @@ class Solver:
         except Exception:
             pass
 
+    @property
+    def num_instances(self) -> int:
+        return len(self.shapes)
+
     # -- iteration ---------------------------------------------------------------
     def iterate(self, n: int):
         self._check(self.lib.opf_iterate(self.ctx, int(n)))
@@ -240,42 +265,54 @@ class Solver:
         d["status"] = STATUS[st]
         return d
 
-    def residuals(self) -> Dict:
+    def reset(self):
+        self._check(self.lib.opf_reset(self.ctx))
+
+    def residuals(self, instance: int = 0) -> Dict:
         r = Resid()
-        self._check(self.lib.opf_residuals(self.ctx, byref(r)))
+        self._check(self.lib.opf_residuals_i(self.ctx, int(instance), byref(r)))
         return r.as_dict()
 
-    def history(self, max_records: int = 4096) -> List[Dict]:
+    def history(self, max_records: int = 4096, instance: int = 0) -> List[Dict]:
         buf = (Resid * max_records)()
         n = c_int32()
-        self._check(self.lib.opf_residual_history(self.ctx, buf, max_records, byref(n)))
+        self._check(self.lib.opf_residual_history_i(self.ctx, int(instance), buf, max_records,
+                                                    byref(n)))
         return [buf[i].as_dict() for i in range(n.value)]
 
     def synchronize(self):
         self.stream.synchronize()
 
+    def autotune(self, trials: int = 5, cache_path: Optional[str] = None) -> Dict:
+        t = Tuning()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.opf_autotune(self.ctx, int(trials), path, byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}
+
     # -- state -------------------------------------------------------------------
-    def field_device(self, name: str):
+    def field_device(self, name: str, instance: int = 0):
         """One field of the iterate as a float64 device tensor in the paper's
         layout ([K+1][L][T], [K+1][N][T] or [G+D+B][T])."""
         torch = self.torch
         fid = FIELDS[name]
         cnt = c_size_t()
-        self._check(self.lib.opf_field_size(self.ctx, fid, byref(cnt)))
+        self._check(self.lib.opf_field_size_i(self.ctx, int(instance), fid, byref(cnt)))
         out = torch.empty(int(cnt.value), dtype=torch.float64, device=self.device)
-        self._check(self.lib.opf_get_field(self.ctx, fid, c_void_p(out.data_ptr()), cnt))
+        self._check(self.lib.opf_get_field_i(self.ctx, int(instance), fid,
+                                             c_void_p(out.data_ptr()), cnt))
         self.stream.synchronize()
-        Kp = self.K + 1
-        shape = {0: (Kp, self.L, self.T), 5: (Kp, self.N, self.T), 8: (self.Jnc, self.T)}
+        s = self.shapes[instance]
+        Kp = s["K"] + 1
+        shape = {0: (Kp, s["L"], s["T"]), 5: (Kp, s["N"], s["T"]), 8: (s["Jnc"], s["T"])}
         key = 0 if fid <= 4 else (5 if fid <= 7 else 8)
         return out.reshape(shape[key])
 
-    def field(self, name: str):
+    def field(self, name: str, instance: int = 0):
         """One field of the iterate as a float64 CPU tensor."""
-        return self.field_device(name).cpu()
+        return self.field_device(name, instance).cpu()
 
-    def state(self) -> Dict:
-        return {k: self.field(k) for k in FIELDS}
+    def state(self, instance: int = 0) -> Dict:
+        return {k: self.field(k, instance) for k in FIELDS}
 
     # -- timing --------------------------------------------------------------------
     def set_timing(self, enable: bool):

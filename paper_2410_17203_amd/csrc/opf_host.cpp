@@ -1,15 +1,18 @@
 // Host side of the C ABI declared in include/opf.h: validation, the
 // CSR-by-node structure, workspace layout, launch sequencing of one
-// message-passing iteration (Section 3.2 of arXiv 2410.17203), HIP-graph
-// blocks of iterations, the solve loop with FP64 polishing, and per-kernel
-// event timing.
+// message-passing iteration (Section 3.2 of arXiv 2410.17203) for one
+// instance or a batch of instances, HIP-graph blocks of iterations, the
+// solve loop with FP64 polishing, per-kernel event timing and the launch
+// autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -21,8 +24,8 @@ using namespace opf;
 namespace {
 
 constexpr size_t kAlign = 256;
-// Upper bound of the sweep grid (partials are sized for it); the grid used
-// is the number of blocks resident at once on the device.
+// Upper bound of the sweep grid (partials are sized for it); the grid used is
+// the number of blocks resident at once on the device times a tuning factor.
 constexpr int kMaxSweepBlocks = 8192;
 
 thread_local std::string g_create_error;
@@ -39,18 +42,42 @@ struct Layout {
   }
 };
 
-// Offsets of one precision's iterate inside the workspace.
 struct BufOffsets {
   size_t P, Tm, V1, V2, Td, U, W, TB;
 };
 struct StateOffsets {
   BufOffsets buf[2];
   size_t avgW, avgTB, pnc, thnc, vbar, ramp, bat;
+  size_t begin, end;
 };
 
 struct Timed {
   int kind;
   hipEvent_t a, b;
+};
+
+// One loaded instance.
+struct Inst {
+  int N = 0, T = 0, K = 0, Kp = 0, Kpp = 0, L = 0, G = 0, D = 0, B = 0, Jnc = 0, nR = 0;
+  double eps_eff = 0.0, rms_norm = 1.0;
+  Topo topo{};
+  Geom geom64{}, geom32{};
+  State<double, double> st64{};
+  State<float, float> st32{};
+  State<float, bf16_t> st32b{};
+  Ctl* ctl = nullptr;
+  Rec* ring = nullptr;
+  size_t state_begin = 0, state_end = 0;  // workspace range of the iterate
+};
+
+// Offsets of everything one instance holds in the workspace.
+struct InstPlan {
+  size_t ctl, ring;
+  size_t line_from, line_to, sus, cap, outage_k, node_lptr, node_lterm, node_nptr, node_nterm, deg,
+      nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
+      bat_eta, bat_alpha;
+  size_t part_sweep, part_nc;
+  StateOffsets o64{}, o32{};
 };
 
 }  // namespace
@@ -60,25 +87,28 @@ struct opf_ctx {
   std::string err;
   hipStream_t stream = nullptr;
   bool loaded = false;
-  // sizes
-  int N = 0, T = 0, K = 0, Kp = 0, Kpp = 0, L = 0, G = 0, D = 0, B = 0, Jnc = 0, nR = 0;
-  double eps_eff = 0.0, rms_norm = 1.0;
-  // workspace
+  bool batch = false;
+  std::vector<Inst> inst;
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  Topo topo{};
-  Geom geom64{}, geom32{};
   bool has64 = false, has32 = false;
-  State<double, double> st64{};
-  State<float, float> st32{};
-  State<float, bf16_t> st32b{};
   int precision = 0;  // 0 = FP64 iterate active, 1 = FP32
   bool bf16_duals = false;
   int64_t host_iter = 0;
-  Ctl* ctl = nullptr;
-  Rec* ring = nullptr;
+  int max_T = 1;
+  // batch work lists (device) and their descriptors per precision
+  BatchTab tab64{}, tab32{};
+  void* d_descs64 = nullptr;
+  void* d_descs32 = nullptr;
+  int64_t* d_dev_prefix = nullptr;
+  int64_t* d_grp64 = nullptr;
+  int64_t* d_grp32 = nullptr;
+  // launch tuning
+  int lanes_shift = 0;       // lanes per row = natural value << shift (or >>)
+  double grid_factor = 1.0;  // sweep grid = resident blocks * factor
   // pinned readback buffers
   Ctl* h_ctl = nullptr;
+  int h_ctl_count = 0;
   Rec* h_rec = nullptr;
   int32_t* h_int = nullptr;
   // timing
@@ -110,8 +140,7 @@ opf_status fail(opf_ctx* c, opf_status s, const std::string& msg) {
 
 bool finite(double x) { return std::isfinite(x); }
 
-// Validates the network; on success fills the derived sizes into c (not
-// committed until load succeeds).
+// Validates one network against the context's options.
 opf_status validate(opf_ctx* c, const opf_network* n) {
   if (!n) return fail(c, OPF_E_INVALID, "network is NULL");
   if (n->N < 1) return fail(c, OPF_E_INVALID, "N must be >= 1");
@@ -159,8 +188,7 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
     deg[n->gen_node[g]]++;
     if (!(n->gen_c2[g] > 0.0) || !finite(n->gen_c2[g]) || !finite(n->gen_c1[g]))
       return fail(c, OPF_E_INVALID, "generator costs must be finite with c2 > 0");
-    const double r = n->gen_ramp[g];
-    if (std::isnan(r)) return fail(c, OPF_E_INVALID, "generator ramp is NaN");
+    if (std::isnan(n->gen_ramp[g])) return fail(c, OPF_E_INVALID, "generator ramp is NaN");
     for (int t = 0; t < T; ++t) {
       const double lo = n->gen_pmin[size_t(g) * T + t], hi = n->gen_pmax[size_t(g) * T + t];
       if (!finite(lo) || !finite(hi) || lo > hi)
@@ -188,51 +216,80 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
   return OPF_OK;
 }
 
-void make_geom(opf_ctx* c, int vec, Geom& g) {
-  g.nv = c->Kpp / vec;
-  g.n_nc_blocks = (c->Jnc + 3) / 4;
+void set_sizes(Inst& s, const opf_network* n) {
+  s.N = n->N;
+  s.T = n->T;
+  s.K = n->K;
+  s.Kp = n->K + 1;
+  s.Kpp = (s.Kp + 3) / 4 * 4;
+  s.L = n->L;
+  s.G = n->G;
+  s.D = n->D;
+  s.B = n->B;
+  s.Jnc = n->G + n->D + n->B;
+  s.nR = 0;
+  if (n->T > 1)
+    for (int g = 0; g < n->G; ++g)
+      if (n->gen_ramp[g] > 0.0 && std::isfinite(n->gen_ramp[g])) s.nR++;
+}
+
+// Launch geometry of one instance for 16-byte vectors of `vec` elements;
+// lanes_shift scales the lanes per row (tuning), resident caps the grid.
+void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, Geom& g) {
+  g.nv = s.Kpp / vec;
+  g.n_nc_blocks = (s.Jnc + 3) / 4;
   int lpr = 1;
   while (lpr < g.nv && lpr < kWave) lpr *= 2;
+  if (c->lanes_shift > 0)
+    lpr = std::min(kWave, lpr << c->lanes_shift);
+  else if (c->lanes_shift < 0)
+    lpr = std::max(1, lpr >> (-c->lanes_shift));
   g.lanes_per_row = lpr;
   g.rows_per_grp = (kBlock / kWave) * (kWave / lpr);
-  const int64_t NT = int64_t(c->N) * c->T;
+  const int64_t NT = int64_t(s.N) * s.T;
   g.n_grps = (NT + g.rows_per_grp - 1) / g.rows_per_grp;
   g.n_sweep_blocks = std::max(8, round8(std::min<int64_t>(g.n_grps, kMaxSweepBlocks)));
+  if (resident >= 8) {
+    const int cap = std::min(kMaxSweepBlocks, std::max(8, int(resident * c->grid_factor) / 8 * 8));
+    g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
+  }
   g.inner_iters = c->opt.inner_iters;
   g.omega_scale = c->opt.inner_omega_scale;
 }
 
 template <typename R, typename VT>
-void state_offsets(opf_ctx* c, Layout& lay, StateOffsets& o) {
-  const size_t line = size_t(c->L) * c->T * c->Kpp;
-  const size_t node = size_t(c->N) * c->T * c->Kpp;
+void state_offsets(const Inst& s, Layout& lay, StateOffsets& o) {
+  const size_t line = size_t(s.L) * s.T * s.Kpp;
+  const size_t node = size_t(s.N) * s.T * s.Kpp;
+  o.begin = lay.total;
   for (int i = 0; i < 2; ++i) {
     BufOffsets& b = o.buf[i];
     b.P = lay.take(line * sizeof(R));
     b.Tm = lay.take(line * sizeof(R));
     b.V1 = lay.take(line * sizeof(VT));
     b.V2 = lay.take(line * sizeof(VT));
-    b.Td = lay.take(size_t(c->T) * c->Kpp * sizeof(R));
+    b.Td = lay.take(size_t(s.T) * s.Kpp * sizeof(R));
     b.U = lay.take(node * sizeof(R));
     b.W = lay.take(node * sizeof(R));
     b.TB = lay.take(node * sizeof(R));
   }
-  o.avgW = lay.take(size_t(c->N) * c->T * sizeof(R));
-  o.avgTB = lay.take(size_t(c->N) * c->T * sizeof(R));
-  const size_t nc = size_t(c->Jnc) * c->T;
+  o.avgW = lay.take(size_t(s.N) * s.T * sizeof(R));
+  o.avgTB = lay.take(size_t(s.N) * s.T * sizeof(R));
+  const size_t nc = size_t(s.Jnc) * s.T;
   o.pnc = lay.take(nc * sizeof(R));
   o.thnc = lay.take(nc * sizeof(R));
   o.vbar = lay.take(nc * sizeof(R));
-  o.ramp = lay.take(4 * size_t(c->nR) * c->T * sizeof(R));
-  o.bat = lay.take(6 * size_t(c->B) * c->T * sizeof(R));
+  o.ramp = lay.take(4 * size_t(s.nR) * s.T * sizeof(R));
+  o.bat = lay.take(6 * size_t(s.B) * s.T * sizeof(R));
+  o.end = lay.total;
 }
 
 template <typename R, typename VT>
 State<R, VT> state_ptrs(char* ws, const StateOffsets& o) {
-  State<R, VT> s;
+  State<R, VT> st;
   for (int i = 0; i < 2; ++i) {
     const BufOffsets& b = o.buf[i];
-    Buf<R, VT>& d = s.buf[i];
+    Buf<R, VT>& d = st.buf[i];
     d.P = reinterpret_cast<R*>(ws + b.P);
     d.Tm = reinterpret_cast<R*>(ws + b.Tm);
     d.V1 = reinterpret_cast<VT*>(ws + b.V1);
@@ -242,96 +299,75 @@ State<R, VT> state_ptrs(char* ws, const StateOffsets& o) {
     d.W = reinterpret_cast<R*>(ws + b.W);
     d.TB = reinterpret_cast<R*>(ws + b.TB);
   }
-  s.avgW = reinterpret_cast<R*>(ws + o.avgW);
-  s.avgTB = reinterpret_cast<R*>(ws + o.avgTB);
-  s.pnc = reinterpret_cast<R*>(ws + o.pnc);
-  s.thnc = reinterpret_cast<R*>(ws + o.thnc);
-  s.vbar = reinterpret_cast<R*>(ws + o.vbar);
-  s.ramp_st = reinterpret_cast<R*>(ws + o.ramp);
-  s.bat_st = reinterpret_cast<R*>(ws + o.bat);
-  return s;
+  st.avgW = reinterpret_cast<R*>(ws + o.avgW);
+  st.avgTB = reinterpret_cast<R*>(ws + o.avgTB);
+  st.pnc = reinterpret_cast<R*>(ws + o.pnc);
+  st.thnc = reinterpret_cast<R*>(ws + o.thnc);
+  st.vbar = reinterpret_cast<R*>(ws + o.vbar);
+  st.ramp_st = reinterpret_cast<R*>(ws + o.ramp);
+  st.bat_st = reinterpret_cast<R*>(ws + o.bat);
+  return st;
 }
 
-// Everything the workspace holds, in order.
-struct Plan {
-  Layout lay;
-  size_t ctl, ring;
-  size_t line_from, line_to, sus, cap, outage_k, node_lptr, node_lterm, node_nptr, node_nterm, deg,
-      nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
-      bat_eta, bat_alpha;
-  size_t part_sweep, part_nc;
-  size_t state_begin, state_end;
-  bool has64 = false, has32 = false;
-  StateOffsets o64{}, o32{};
-};
-
-void make_plan(opf_ctx* c, Plan& p) {
-  Layout& L = p.lay;
+void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
   p.ctl = L.take(sizeof(Ctl));
   p.ring = L.take(sizeof(Rec) * kRing);
-  const size_t Li = size_t(c->L), Ni = size_t(c->N), Gi = size_t(c->G), T = size_t(c->T);
+  const size_t Li = size_t(s.L), Ni = size_t(s.N), Gi = size_t(s.G), T = size_t(s.T);
   p.line_from = L.take(Li * 4);
   p.line_to = L.take(Li * 4);
   p.sus = L.take(Li * 8);
   p.cap = L.take(Li * 8);
-  p.outage_k = L.take(size_t(c->Kpp) * 4);
+  p.outage_k = L.take(size_t(s.Kpp) * 4);
   p.node_lptr = L.take((Ni + 1) * 4);
   p.node_lterm = L.take(4 * Li * 4);
   p.node_nptr = L.take((Ni + 1) * 4);
-  p.node_nterm = L.take(size_t(c->Jnc) * 4);
+  p.node_nterm = L.take(size_t(s.Jnc) * 4);
   p.deg = L.take(Ni * 8);
-  p.nc_node = L.take(size_t(c->Jnc) * 4);
+  p.nc_node = L.take(size_t(s.Jnc) * 4);
   p.ramp_idx = L.take(Gi * 4);
   p.gen_c2 = L.take(Gi * 8);
   p.gen_c1 = L.take(Gi * 8);
   p.gen_pmin = L.take(Gi * T * 8);
   p.gen_pmax = L.take(Gi * T * 8);
   p.gen_ramp = L.take(Gi * 8);
-  p.load_d = L.take(size_t(c->D) * T * 8);
-  p.bat_P = L.take(size_t(c->B) * 8);
-  p.bat_dur = L.take(size_t(c->B) * 8);
-  p.bat_eta = L.take(size_t(c->B) * 8);
-  p.bat_alpha = L.take(size_t(c->B) * 8);
-  Geom g64{}, g32{};
-  make_geom(c, 2, g64);
-  make_geom(c, 4, g32);
-  const int nsb = std::max(g64.n_sweep_blocks, g32.n_sweep_blocks);
-  p.part_sweep = L.take(size_t(nsb) * 5 * 8);
-  p.part_nc = L.take(size_t(std::max(g64.n_nc_blocks, 1)) * 2 * 8);
-  p.state_begin = L.total;
-  p.has32 = c->opt.state_dtype == OPF_F32;
-  p.has64 = !p.has32 || c->opt.polish_fp64;
-  if (p.has64) state_offsets<double, double>(c, L, p.o64);
-  if (p.has32) {
+  p.load_d = L.take(size_t(s.D) * T * 8);
+  p.bat_P = L.take(size_t(s.B) * 8);
+  p.bat_dur = L.take(size_t(s.B) * 8);
+  p.bat_eta = L.take(size_t(s.B) * 8);
+  p.bat_alpha = L.take(size_t(s.B) * 8);
+  // residual partials: per sweep block (single instance) or per (row group,
+  // wave) (batch, at most one per row plus a block); per device block or per
+  // device
+  const size_t NT = Ni * T;
+  p.part_sweep = L.take(std::max<size_t>(kMaxSweepBlocks, NT + kBlock) * 5 * 8);
+  p.part_nc = L.take(std::max<size_t>(s.Jnc, 1) * 2 * 8);
+  const bool has32 = c->opt.state_dtype == OPF_F32;
+  const bool has64 = !has32 || c->opt.polish_fp64;
+  if (has64) state_offsets<double, double>(s, L, p.o64);
+  if (has32) {
     if (c->opt.dual_dtype == OPF_BF16)
-      state_offsets<float, bf16_t>(c, L, p.o32);
+      state_offsets<float, bf16_t>(s, L, p.o32);
     else
-      state_offsets<float, float>(c, L, p.o32);
+      state_offsets<float, float>(s, L, p.o32);
   }
-  p.state_end = L.total;
 }
 
-void set_sizes(opf_ctx* c, const opf_network* n) {
-  c->N = n->N;
-  c->T = n->T;
-  c->K = n->K;
-  c->Kp = n->K + 1;
-  c->Kpp = (c->Kp + 3) / 4 * 4;
-  c->L = n->L;
-  c->G = n->G;
-  c->D = n->D;
-  c->B = n->B;
-  c->Jnc = n->G + n->D + n->B;
-  c->nR = 0;
-  if (n->T > 1)
-    for (int g = 0; g < n->G; ++g)
-      if (n->gen_ramp[g] > 0.0 && std::isfinite(n->gen_ramp[g])) c->nR++;
+struct BatchPlan {
+  size_t descs64, descs32, dev_prefix, grp64, grp32;
+};
+
+void plan_batch(int count, Layout& L, BatchPlan& b) {
+  b.descs64 = L.take(sizeof(KArgs<double, double>) * count);
+  b.descs32 = L.take(sizeof(KArgs<float, float>) * count);
+  b.dev_prefix = L.take(sizeof(int64_t) * (count + 1));
+  b.grp64 = L.take(sizeof(int64_t) * (count + 1));
+  b.grp32 = L.take(sizeof(int64_t) * (count + 1));
 }
 
 template <typename R, typename VT>
-KArgs<R, VT> kargs(opf_ctx* c, const State<R, VT>& st, const Geom& g) {
+KArgs<R, VT> kargs(const Inst& s, const State<R, VT>& st, const Geom& g) {
   KArgs<R, VT> a;
-  a.tp = c->topo;
+  a.tp = s.topo;
   a.st = st;
   a.g = g;
   return a;
@@ -366,80 +402,479 @@ void timed(opf_ctx* c, int kind, Fn fn, bool capturing) {
   c->pending.push_back({kind, a, b});
 }
 
+bool adapt_after(const opf_ctx* c, int64_t iter_index) {
+  const int ae = c->opt.adapt_every;
+  return ae > 0 && (iter_index + 1) % ae == 0;
+}
+
 template <typename R, typename VT>
 void enqueue_iter(opf_ctx* c, const KArgs<R, VT>& a, int64_t iter_index, bool capturing) {
-  // iter_index: 0-based index of this iteration since the start
   timed(c, OPF_KERNEL_DEVICES, [&] { launch_devices(a, c->stream); }, capturing);
   timed(c, OPF_KERNEL_SWEEP, [&] { launch_sweep(a, c->stream); }, capturing);
   timed(c, OPF_KERNEL_FINALIZE, [&] { launch_finalize(a, c->stream); }, capturing);
-  const int ae = c->opt.adapt_every;
-  if (ae > 0 && (iter_index + 1) % ae == 0)
+  if (adapt_after(c, iter_index))
     timed(c, OPF_KERNEL_RESCALE, [&] { launch_rescale(a, c->stream); }, capturing);
+}
+
+template <typename R, typename VT>
+void enqueue_batch_iter(opf_ctx* c, const BatchTab& tab, int64_t iter_index, bool capturing) {
+  timed(c, OPF_KERNEL_DEVICES,
+        [&] { launch_batch_iter_devices<R, VT>(tab, c->max_T, c->stream); }, capturing);
+  timed(c, OPF_KERNEL_SWEEP, [&] { launch_batch_iter_sweep<R, VT>(tab, c->stream); }, capturing);
+  timed(c, OPF_KERNEL_FINALIZE, [&] { launch_batch_iter_finalize<R, VT>(tab, c->stream); },
+        capturing);
+  if (adapt_after(c, iter_index))
+    timed(c, OPF_KERNEL_RESCALE, [&] { launch_batch_iter_rescale<R, VT>(tab, c->stream); },
+          capturing);
 }
 
 void enqueue_n(opf_ctx* c, int n, bool capturing, int64_t start) {
   for (int i = 0; i < n; ++i) {
     const int64_t it = start + i;
+    if (c->batch) {
+      if (c->precision == 0)
+        enqueue_batch_iter<double, double>(c, c->tab64, it, capturing);
+      else if (c->bf16_duals)
+        enqueue_batch_iter<float, bf16_t>(c, c->tab32, it, capturing);
+      else
+        enqueue_batch_iter<float, float>(c, c->tab32, it, capturing);
+      continue;
+    }
+    const Inst& s = c->inst[0];
     if (c->precision == 0)
-      enqueue_iter(c, kargs(c, c->st64, c->geom64), it, capturing);
+      enqueue_iter(c, kargs(s, s.st64, s.geom64), it, capturing);
     else if (c->bf16_duals)
-      enqueue_iter(c, kargs(c, c->st32b, c->geom32), it, capturing);
+      enqueue_iter(c, kargs(s, s.st32b, s.geom32), it, capturing);
     else
-      enqueue_iter(c, kargs(c, c->st32, c->geom32), it, capturing);
+      enqueue_iter(c, kargs(s, s.st32, s.geom32), it, capturing);
   }
 }
 
-opf_status read_ctl(opf_ctx* c) {
-  HIP_TRY(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+// Copies every instance's control block to the pinned host array.
+opf_status read_ctls(opf_ctx* c) {
+  for (size_t i = 0; i < c->inst.size(); ++i)
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctl + i, c->inst[i].ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                              c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return OPF_OK;
 }
 
-opf_status last_record(opf_ctx* c, opf_resid* out) {
-  opf_status s = read_ctl(c);
-  if (s != OPF_OK) return s;
+void fill_resid(const Rec& r, opf_resid* o) {
+  o->primal_p = r.primal_p;
+  o->primal_theta = r.primal_th;
+  o->dual_p = r.dual_p;
+  o->dual_theta = r.dual_th;
+  o->rms_primal = r.rms_primal;
+  o->rms_dual = r.rms_dual;
+  o->threshold = r.threshold;
+  o->objective = r.objective;
+  o->rho_p = r.rho_p;
+  o->rho_theta = r.rho_th;
+  o->converged = r.converged;
+  o->precision = r.precision == 0 ? OPF_F64 : OPF_F32;
+}
+
+// Last residual record of instance i (control blocks must be fresh).
+opf_status last_record(opf_ctx* c, int i, opf_resid* out) {
   std::memset(out, 0, sizeof(*out));
-  const int iter = c->h_ctl->iter;
+  const Inst& s = c->inst[i];
+  const Ctl& h = c->h_ctl[i];
   const int ce = std::max(1, c->opt.check_every);
-  const int last = iter - iter % ce;
-  out->iter = iter;
-  out->rho_p = c->h_ctl->rho_p;
-  out->rho_theta = c->h_ctl->rho_th;
-  out->threshold = c->eps_eff;
+  const int last = h.iter - h.iter % ce;
+  out->iter = h.iter;
+  out->rho_p = h.rho_p;
+  out->rho_theta = h.rho_th;
+  out->threshold = s.eps_eff;
   out->precision = c->precision == 0 ? OPF_F64 : OPF_F32;
   if (last <= 0) return OPF_OK;
-  HIP_TRY(c, hipMemcpyAsync(c->h_rec, c->ring + (last - 1) % kRing, sizeof(Rec),
+  HIP_TRY(c, hipMemcpyAsync(c->h_rec, s.ring + (last - 1) % kRing, sizeof(Rec),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const Rec& r = *c->h_rec;
-  out->primal_p = r.primal_p;
-  out->primal_theta = r.primal_th;
-  out->dual_p = r.dual_p;
-  out->dual_theta = r.dual_th;
-  out->rms_primal = r.rms_primal;
-  out->rms_dual = r.rms_dual;
-  out->threshold = r.threshold;
-  out->objective = r.objective;
-  out->rho_p = r.rho_p;
-  out->rho_theta = r.rho_th;
-  out->converged = r.converged;
-  out->precision = r.precision == 0 ? OPF_F64 : OPF_F32;
+  fill_resid(*c->h_rec, out);
+  out->iter = h.iter;
   return OPF_OK;
 }
 
 opf_status widen_to_fp64(opf_ctx* c) {
-  KArgs<double, double> dst = kargs(c, c->st64, c->geom64);
-  if (c->bf16_duals)
-    launch_widen(kargs(c, c->st32b, c->geom32), dst, c->stream);
-  else
-    launch_widen(kargs(c, c->st32, c->geom32), dst, c->stream);
-  HIP_TRY(c, hipGetLastError());
-  *c->h_int = 0;
-  HIP_TRY(c, hipMemcpyAsync(&c->ctl->precision, c->h_int, sizeof(int32_t), hipMemcpyHostToDevice,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (Inst& s : c->inst) {
+    KArgs<double, double> dst = kargs(s, s.st64, s.geom64);
+    if (c->bf16_duals)
+      launch_widen(kargs(s, s.st32b, s.geom32), dst, c->stream);
+    else
+      launch_widen(kargs(s, s.st32, s.geom32), dst, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    *c->h_int = 0;
+    HIP_TRY(c, hipMemcpyAsync(&s.ctl->precision, c->h_int, sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   c->precision = 0;
   return OPF_OK;
+}
+
+// (Re)computes every instance's launch geometry and the batch work lists.
+opf_status refresh_geometry(opf_ctx* c) {
+  int res64 = 0, res32 = 0;
+  if (c->batch) {
+    res64 = sweep_batch_resident_blocks<double, double>();
+    res32 = c->bf16_duals ? sweep_batch_resident_blocks<float, bf16_t>()
+                          : sweep_batch_resident_blocks<float, float>();
+  } else {
+    res64 = sweep_resident_blocks<double, double>();
+    res32 = c->bf16_duals ? sweep_resident_blocks<float, bf16_t>()
+                          : sweep_resident_blocks<float, float>();
+  }
+  for (Inst& s : c->inst) {
+    for (int p = 0; p < 2; ++p) {
+      Geom& g = p == 0 ? s.geom64 : s.geom32;
+      const Geom keep = g;  // scratch pointers are fixed at load
+      make_geom(c, s, p == 0 ? 2 : 4, p == 0 ? res64 : res32, g);
+      g.part_sweep = keep.part_sweep;
+      g.part_nc = keep.part_nc;
+      g.ctl = keep.ctl;
+      g.ring = keep.ring;
+    }
+  }
+  if (!c->batch) return OPF_OK;
+  const int n = int(c->inst.size());
+  std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0);
+  std::vector<KArgs<double, double>> d64(n);
+  std::vector<KArgs<float, float>> d32(n);
+  std::vector<KArgs<float, bf16_t>> d32b(n);
+  for (int i = 0; i < n; ++i) {
+    const Inst& s = c->inst[i];
+    dev[i + 1] = dev[i] + s.Jnc;
+    g64[i + 1] = g64[i] + s.geom64.n_grps;
+    g32[i + 1] = g32[i] + s.geom32.n_grps;
+    d64[i] = kargs(s, s.st64, s.geom64);
+    d32[i] = kargs(s, s.st32, s.geom32);
+    d32b[i] = kargs(s, s.st32b, s.geom32);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_descs64, d64.data(), sizeof(KArgs<double, double>) * n,
+                            hipMemcpyHostToDevice, c->stream));
+  if (c->bf16_duals)
+    HIP_TRY(c, hipMemcpyAsync(c->d_descs32, d32b.data(), sizeof(KArgs<float, bf16_t>) * n,
+                              hipMemcpyHostToDevice, c->stream));
+  else
+    HIP_TRY(c, hipMemcpyAsync(c->d_descs32, d32.data(), sizeof(KArgs<float, float>) * n,
+                              hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_dev_prefix, dev.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_grp64, g64.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_grp32, g32.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  auto tab = [&](BatchTab& t, const void* descs, const int64_t* grp, int64_t total_grps, int res) {
+    t.descs = descs;
+    t.dev_prefix = c->d_dev_prefix;
+    t.grp_prefix = grp;
+    t.n_inst = n;
+    t.total_dev = dev[n];
+    t.total_grps = total_grps;
+    int nb = std::max(8, round8(std::min<int64_t>(total_grps, kMaxSweepBlocks)));
+    if (res >= 8)
+      nb = std::max(8, std::min(nb, std::min(kMaxSweepBlocks,
+                                             std::max(8, int(res * c->grid_factor) / 8 * 8))));
+    t.n_sweep_blocks = nb;
+  };
+  tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64);
+  tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32);
+  return OPF_OK;
+}
+
+// Resets every instance to the all-zero start (Section 3.4).
+opf_status reset_state(opf_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  for (size_t i = 0; i < c->inst.size(); ++i) {
+    Inst& s = c->inst[i];
+    if (s.state_end > s.state_begin)
+      HIP_TRY(c, hipMemsetAsync(c->ws + s.state_begin, 0, s.state_end - s.state_begin, c->stream));
+    Ctl& h = c->h_ctl[i];
+    std::memset(&h, 0, sizeof(Ctl));
+    h.rho_p = c->opt.rho_p;
+    h.rho_th = c->opt.rho_theta;
+    h.su = 1.0;
+    h.sv = 1.0;
+    h.eps_eff = s.eps_eff;
+    h.rms_norm = s.rms_norm;
+    h.mu = c->opt.mu;
+    h.gamma = c->opt.gamma;
+    h.adapt_every = c->opt.adapt_every;
+    h.check_every = c->opt.check_every;
+    h.max_iter = c->opt.max_iter;
+    h.min_iter = c->opt.min_iter;
+    h.precision = c->has32 ? 1 : 0;
+    HIP_TRY(c, hipMemcpyAsync(s.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->precision = c->has32 ? 1 : 0;
+  c->host_iter = 0;
+  return OPF_OK;
+}
+
+// Validates all networks and lays out the workspace.
+opf_status plan_all(opf_ctx* c, const opf_network* nets, int count, std::vector<Inst>& insts,
+                    std::vector<InstPlan>& plans, BatchPlan& bp, Layout& lay) {
+  if (count < 1) return fail(c, OPF_E_INVALID, "need at least one network");
+  if (!nets) return fail(c, OPF_E_INVALID, "networks are NULL");
+  insts.assign(count, Inst());
+  plans.assign(count, InstPlan());
+  for (int i = 0; i < count; ++i) {
+    opf_status s = validate(c, &nets[i]);
+    if (s != OPF_OK) {
+      if (count > 1) c->err = "instance " + std::to_string(i) + ": " + c->err;
+      return s;
+    }
+    set_sizes(insts[i], &nets[i]);
+  }
+  if (count > 1) plan_batch(count, lay, bp);
+  for (int i = 0; i < count; ++i) plan_instance(c, insts[i], lay, plans[i]);
+  return OPF_OK;
+}
+
+opf_status workspace_size(opf_ctx* c, const opf_network* nets, int count, size_t* bytes) {
+  if (!c || !bytes) return fail(c, OPF_E_INVALID, "NULL argument");
+  std::vector<Inst> insts;
+  std::vector<InstPlan> plans;
+  BatchPlan bp{};
+  Layout lay;
+  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay);
+  if (s != OPF_OK) return s;
+  *bytes = lay.total;
+  return OPF_OK;
+}
+
+// Builds the derived host data of one network and copies it to the device.
+opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const InstPlan& p) {
+  char* ws = c->ws;
+  const int N = s.N, T = s.T, L = s.L, G = s.G, D = s.D, B = s.B, Jnc = s.Jnc, Kpp = s.Kpp;
+  std::vector<int32_t> outage_k(Kpp, -1);
+  for (int k = 1; k <= s.K; ++k) outage_k[k] = n->outage[k - 1];
+  // CSR by node: line terminals ordered (terminal 1 by line, then terminal 2
+  // by line), then generators, loads, batteries.
+  std::vector<int32_t> lptr(N + 1, 0), nptr(N + 1, 0), lterm(4 * size_t(L)), nterm(Jnc), nc_node(Jnc);
+  for (int l = 0; l < L; ++l) {
+    lptr[n->line_from[l] + 1]++;
+    lptr[n->line_to[l] + 1]++;
+  }
+  for (int v = 0; v < N; ++v) lptr[v + 1] += lptr[v];
+  {
+    std::vector<int32_t> fill(lptr.begin(), lptr.end() - 1);
+    // entry: (2 l + end, node at the other end of the line)
+    for (int l = 0; l < L; ++l) {
+      const int q = fill[n->line_from[l]]++;
+      lterm[2 * size_t(q)] = 2 * l;
+      lterm[2 * size_t(q) + 1] = n->line_to[l];
+    }
+    for (int l = 0; l < L; ++l) {
+      const int q = fill[n->line_to[l]]++;
+      lterm[2 * size_t(q)] = 2 * l + 1;
+      lterm[2 * size_t(q) + 1] = n->line_from[l];
+    }
+  }
+  for (int g = 0; g < G; ++g) nc_node[g] = n->gen_node[g];
+  for (int d = 0; d < D; ++d) nc_node[G + d] = n->load_node[d];
+  for (int b = 0; b < B; ++b) nc_node[G + D + b] = n->bat_node[b];
+  for (int j = 0; j < Jnc; ++j) nptr[nc_node[j] + 1]++;
+  for (int v = 0; v < N; ++v) nptr[v + 1] += nptr[v];
+  {
+    std::vector<int32_t> fill(nptr.begin(), nptr.end() - 1);
+    for (int j = 0; j < Jnc; ++j) nterm[fill[nc_node[j]]++] = j;
+  }
+  std::vector<double> deg(N);
+  for (int v = 0; v < N; ++v) deg[v] = double(lptr[v + 1] - lptr[v] + nptr[v + 1] - nptr[v]);
+  std::vector<int32_t> ramp_idx(G, -1);
+  {
+    int r = 0;
+    if (T > 1)
+      for (int g = 0; g < G; ++g)
+        if (n->gen_ramp[g] > 0.0 && std::isfinite(n->gen_ramp[g])) ramp_idx[g] = r++;
+  }
+  double lsum = 0.0;
+  for (size_t i = 0; i < size_t(D) * T; ++i) lsum += n->load_d[i] * n->load_d[i];
+  const double load_rms = (size_t(D) * T > 0) ? std::sqrt(lsum / double(size_t(D) * T)) : 1.0;
+
+  auto up = [&](size_t off, const void* src, size_t nbytes) -> hipError_t {
+    if (nbytes == 0) return hipSuccess;
+    return hipMemcpyAsync(ws + off, src, nbytes, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_TRY(c, up(p.line_from, n->line_from, size_t(L) * 4));
+  HIP_TRY(c, up(p.line_to, n->line_to, size_t(L) * 4));
+  HIP_TRY(c, up(p.sus, n->line_sus, size_t(L) * 8));
+  HIP_TRY(c, up(p.cap, n->line_cap, size_t(L) * 8));
+  HIP_TRY(c, up(p.outage_k, outage_k.data(), size_t(Kpp) * 4));
+  HIP_TRY(c, up(p.node_lptr, lptr.data(), size_t(N + 1) * 4));
+  HIP_TRY(c, up(p.node_lterm, lterm.data(), lterm.size() * 4));
+  HIP_TRY(c, up(p.node_nptr, nptr.data(), size_t(N + 1) * 4));
+  HIP_TRY(c, up(p.node_nterm, nterm.data(), nterm.size() * 4));
+  HIP_TRY(c, up(p.deg, deg.data(), size_t(N) * 8));
+  HIP_TRY(c, up(p.nc_node, nc_node.data(), size_t(Jnc) * 4));
+  HIP_TRY(c, up(p.ramp_idx, ramp_idx.data(), size_t(G) * 4));
+  HIP_TRY(c, up(p.gen_c2, n->gen_c2, size_t(G) * 8));
+  HIP_TRY(c, up(p.gen_c1, n->gen_c1, size_t(G) * 8));
+  HIP_TRY(c, up(p.gen_pmin, n->gen_pmin, size_t(G) * T * 8));
+  HIP_TRY(c, up(p.gen_pmax, n->gen_pmax, size_t(G) * T * 8));
+  HIP_TRY(c, up(p.gen_ramp, n->gen_ramp, size_t(G) * 8));
+  HIP_TRY(c, up(p.load_d, n->load_d, size_t(D) * T * 8));
+  HIP_TRY(c, up(p.bat_P, n->bat_P, size_t(B) * 8));
+  HIP_TRY(c, up(p.bat_dur, n->bat_dur, size_t(B) * 8));
+  HIP_TRY(c, up(p.bat_eta, n->bat_eta, size_t(B) * 8));
+  HIP_TRY(c, up(p.bat_alpha, n->bat_alpha, size_t(B) * 8));
+  // synchronise before the host vectors go out of scope
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+
+  Topo& tp = s.topo;
+  tp.N = N; tp.T = T; tp.K = s.K; tp.Kp = s.Kp; tp.Kpp = Kpp; tp.L = L; tp.G = G;
+  tp.D = D; tp.B = B; tp.Jnc = Jnc; tp.nR = s.nR;
+  tp.line_from = reinterpret_cast<const int32_t*>(ws + p.line_from);
+  tp.line_to = reinterpret_cast<const int32_t*>(ws + p.line_to);
+  tp.sus = reinterpret_cast<const double*>(ws + p.sus);
+  tp.cap = reinterpret_cast<const double*>(ws + p.cap);
+  tp.outage_k = reinterpret_cast<const int32_t*>(ws + p.outage_k);
+  tp.node_lptr = reinterpret_cast<const int32_t*>(ws + p.node_lptr);
+  tp.node_lterm = reinterpret_cast<const int2*>(ws + p.node_lterm);
+  tp.node_nptr = reinterpret_cast<const int32_t*>(ws + p.node_nptr);
+  tp.node_nterm = reinterpret_cast<const int32_t*>(ws + p.node_nterm);
+  tp.deg = reinterpret_cast<const double*>(ws + p.deg);
+  tp.nc_node = reinterpret_cast<const int32_t*>(ws + p.nc_node);
+  tp.ramp_idx = reinterpret_cast<const int32_t*>(ws + p.ramp_idx);
+  tp.gen_c2 = reinterpret_cast<const double*>(ws + p.gen_c2);
+  tp.gen_c1 = reinterpret_cast<const double*>(ws + p.gen_c1);
+  tp.gen_pmin = reinterpret_cast<const double*>(ws + p.gen_pmin);
+  tp.gen_pmax = reinterpret_cast<const double*>(ws + p.gen_pmax);
+  tp.gen_ramp = reinterpret_cast<const double*>(ws + p.gen_ramp);
+  tp.load_d = reinterpret_cast<const double*>(ws + p.load_d);
+  tp.bat_P = reinterpret_cast<const double*>(ws + p.bat_P);
+  tp.bat_dur = reinterpret_cast<const double*>(ws + p.bat_dur);
+  tp.bat_eta = reinterpret_cast<const double*>(ws + p.bat_eta);
+  tp.bat_alpha = reinterpret_cast<const double*>(ws + p.bat_alpha);
+
+  s.ctl = reinterpret_cast<Ctl*>(ws + p.ctl);
+  s.ring = reinterpret_cast<Rec*>(ws + p.ring);
+  for (Geom* g : {&s.geom64, &s.geom32}) {
+    g->part_sweep = reinterpret_cast<double*>(ws + p.part_sweep);
+    g->part_nc = reinterpret_cast<double*>(ws + p.part_nc);
+    g->ctl = s.ctl;
+    g->ring = s.ring;
+  }
+  const bool has32 = c->opt.state_dtype == OPF_F32;
+  const bool has64 = !has32 || c->opt.polish_fp64;
+  s.state_begin = SIZE_MAX;
+  s.state_end = 0;
+  if (has64) {
+    s.st64 = state_ptrs<double, double>(ws, p.o64);
+    s.state_begin = std::min(s.state_begin, p.o64.begin);
+    s.state_end = std::max(s.state_end, p.o64.end);
+  }
+  if (has32) {
+    if (c->bf16_duals)
+      s.st32b = state_ptrs<float, bf16_t>(ws, p.o32);
+    else
+      s.st32 = state_ptrs<float, float>(ws, p.o32);
+    s.state_begin = std::min(s.state_begin, p.o32.begin);
+    s.state_end = std::max(s.state_end, p.o32.end);
+  }
+  s.eps_eff = c->opt.eps * (c->opt.eps_relative ? load_rms : 1.0);
+  const double J = 2.0 * L + Jnc;
+  s.rms_norm = std::sqrt(2.0 * J * T * double(s.Kp));
+  return OPF_OK;
+}
+
+opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size_t bytes) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!d_ws) return fail(c, OPF_E_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+    return fail(c, OPF_E_INVALID, "workspace must be 256-byte aligned");
+  std::vector<Inst> insts;
+  std::vector<InstPlan> plans;
+  BatchPlan bp{};
+  Layout lay;
+  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay);
+  if (s != OPF_OK) return s;
+  if (bytes < lay.total)
+    return fail(c, OPF_E_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  if (c->h_ctl_count < count) {
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    c->h_ctl = nullptr;
+    c->h_ctl_count = 0;
+    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_ctl), sizeof(Ctl) * count));
+    c->h_ctl_count = count;
+  }
+  if (!c->h_rec) HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(Rec) * kRing));
+  if (!c->h_int) HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_int), 64));
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->loaded = false;
+  c->ws = static_cast<char*>(d_ws);
+  c->ws_bytes = bytes;
+  c->batch = count > 1;
+  HIP_TRY(c, hipMemsetAsync(c->ws, 0, lay.total, c->stream));
+  c->max_T = 1;
+  for (int i = 0; i < count; ++i) {
+    s = upload_instance(c, &nets[i], insts[i], plans[i]);
+    if (s != OPF_OK) return s;
+    c->max_T = std::max(c->max_T, insts[i].T);
+  }
+  c->inst = std::move(insts);
+  c->has32 = c->opt.state_dtype == OPF_F32;
+  c->has64 = !c->has32 || c->opt.polish_fp64;
+  if (c->batch) {
+    c->d_descs64 = c->ws + bp.descs64;
+    c->d_descs32 = c->ws + bp.descs32;
+    c->d_dev_prefix = reinterpret_cast<int64_t*>(c->ws + bp.dev_prefix);
+    c->d_grp64 = reinterpret_cast<int64_t*>(c->ws + bp.grp64);
+    c->d_grp32 = reinterpret_cast<int64_t*>(c->ws + bp.grp32);
+  }
+  s = refresh_geometry(c);
+  if (s != OPF_OK) return s;
+  s = reset_state(c);
+  if (s != OPF_OK) return s;
+  c->loaded = true;
+  return OPF_OK;
+}
+
+opf_status check_inst(opf_ctx* c, int32_t i) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (i < 0 || i >= int(c->inst.size())) return fail(c, OPF_E_INVALID, "instance out of range");
+  return OPF_OK;
+}
+
+// Enqueues one block of iterations for the solve loop, as a captured graph
+// where possible.
+opf_status enqueue_block(opf_ctx* c, int blk, bool graph_ok) {
+  const int ae = c->opt.adapt_every;
+  const bool aligned = ae == 0 || c->host_iter % ae == 0;
+  if (graph_ok && aligned) {
+    const auto key = std::make_pair(c->precision, blk);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      hipGraph_t gr;
+      HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      enqueue_n(c, blk, true, 0);
+      HIP_TRY(c, hipStreamEndCapture(c->stream, &gr));
+      hipGraphExec_t ex;
+      HIP_TRY(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gr);
+      it = c->graphs.emplace(key, ex).first;
+    }
+    HIP_TRY(c, hipGraphLaunch(it->second, c->stream));
+    c->host_iter += blk;
+  } else {
+    const int n = (graph_ok && !aligned) ? int(ae - c->host_iter % ae) : blk;
+    enqueue_n(c, n, false, c->host_iter);
+    c->host_iter += n;
+  }
+  HIP_TRY(c, hipGetLastError());
+  return OPF_OK;
+}
+
+bool all_done(const opf_ctx* c) {
+  for (size_t i = 0; i < c->inst.size(); ++i)
+    if (!c->h_ctl[i].done) return false;
+  return true;
 }
 
 }  // namespace
@@ -502,200 +937,33 @@ opf_status opf_create(const opf_options* opt, opf_ctx** out) {
 }
 
 opf_status opf_workspace_size(opf_ctx* c, const opf_network* n, size_t* bytes) {
-  if (!c || !bytes) return fail(c, OPF_E_INVALID, "NULL argument");
-  opf_ctx probe;
-  probe.opt = c->opt;
-  opf_status s = validate(&probe, n);
-  if (s != OPF_OK) return fail(c, s, probe.err);
-  set_sizes(&probe, n);
-  Plan p;
-  make_plan(&probe, p);
-  *bytes = p.lay.total;
-  return OPF_OK;
+  return workspace_size(c, n, 1, bytes);
+}
+
+opf_status opf_workspace_size_batch(opf_ctx* c, const opf_network* nets, int32_t count,
+                                    size_t* bytes) {
+  return workspace_size(c, nets, count, bytes);
 }
 
 opf_status opf_load_network(opf_ctx* c, const opf_network* n, void* d_ws, size_t bytes) {
-  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!d_ws) return fail(c, OPF_E_INVALID, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
-    return fail(c, OPF_E_INVALID, "workspace must be 256-byte aligned");
-  opf_ctx probe;
-  probe.opt = c->opt;
-  opf_status s = validate(&probe, n);
-  if (s != OPF_OK) return fail(c, s, probe.err);
-  set_sizes(&probe, n);
-  Plan p;
-  make_plan(&probe, p);
-  if (bytes < p.lay.total)
-    return fail(c, OPF_E_OOM, "workspace too small: need " + std::to_string(p.lay.total) + " bytes");
+  return load(c, n, 1, d_ws, bytes);
+}
 
-  // ---- host-side derived data --------------------------------------------
-  const int N = probe.N, T = probe.T, L = probe.L, G = probe.G, D = probe.D, B = probe.B;
-  const int Jnc = probe.Jnc, Kpp = probe.Kpp;
-  std::vector<int32_t> outage_k(Kpp, -1);
-  for (int k = 1; k <= probe.K; ++k) outage_k[k] = n->outage[k - 1];
-  // CSR by node: line terminals ordered (terminal 1 by line, then terminal 2
-  // by line), then generators, loads, batteries.
-  std::vector<int32_t> lptr(N + 1, 0), nptr(N + 1, 0), lterm(4 * size_t(L)), nterm(Jnc), nc_node(Jnc);
-  for (int l = 0; l < L; ++l) {
-    lptr[n->line_from[l] + 1]++;
-    lptr[n->line_to[l] + 1]++;
-  }
-  for (int v = 0; v < N; ++v) lptr[v + 1] += lptr[v];
-  {
-    std::vector<int32_t> fill(lptr.begin(), lptr.end() - 1);
-    // entry: (2 l + end, node at the other end of the line)
-    for (int l = 0; l < L; ++l) {
-      const int q = fill[n->line_from[l]]++;
-      lterm[2 * size_t(q)] = 2 * l;
-      lterm[2 * size_t(q) + 1] = n->line_to[l];
-    }
-    for (int l = 0; l < L; ++l) {
-      const int q = fill[n->line_to[l]]++;
-      lterm[2 * size_t(q)] = 2 * l + 1;
-      lterm[2 * size_t(q) + 1] = n->line_from[l];
-    }
-  }
-  for (int g = 0; g < G; ++g) nc_node[g] = n->gen_node[g];
-  for (int d = 0; d < D; ++d) nc_node[G + d] = n->load_node[d];
-  for (int b = 0; b < B; ++b) nc_node[G + D + b] = n->bat_node[b];
-  for (int j = 0; j < Jnc; ++j) nptr[nc_node[j] + 1]++;
-  for (int v = 0; v < N; ++v) nptr[v + 1] += nptr[v];
-  {
-    std::vector<int32_t> fill(nptr.begin(), nptr.end() - 1);
-    for (int j = 0; j < Jnc; ++j) nterm[fill[nc_node[j]]++] = j;
-  }
-  std::vector<double> deg(N);
-  for (int v = 0; v < N; ++v) deg[v] = double(lptr[v + 1] - lptr[v] + nptr[v + 1] - nptr[v]);
-  std::vector<int32_t> ramp_idx(G, -1);
-  {
-    int r = 0;
-    if (T > 1)
-      for (int g = 0; g < G; ++g)
-        if (n->gen_ramp[g] > 0.0 && std::isfinite(n->gen_ramp[g])) ramp_idx[g] = r++;
-  }
-  double lsum = 0.0;
-  for (size_t i = 0; i < size_t(D) * T; ++i) lsum += n->load_d[i] * n->load_d[i];
-  const double load_rms = (size_t(D) * T > 0) ? std::sqrt(lsum / double(size_t(D) * T)) : 1.0;
+opf_status opf_load_batch(opf_ctx* c, const opf_network* nets, int32_t count, void* d_ws,
+                          size_t bytes) {
+  return load(c, nets, count, d_ws, bytes);
+}
 
-  // pinned readback buffers (first load only)
-  if (!c->h_ctl) {
-    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_ctl), sizeof(Ctl)));
-    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(Rec) * kRing));
-    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_int), 64));
-  }
-
-  // ---- commit ---------------------------------------------------------------
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
-  c->N = probe.N; c->T = T; c->K = probe.K; c->Kp = probe.Kp; c->Kpp = Kpp;
-  c->L = L; c->G = G; c->D = D; c->B = B; c->Jnc = Jnc; c->nR = probe.nR;
-  c->ws = static_cast<char*>(d_ws);
-  c->ws_bytes = bytes;
-  char* ws = c->ws;
-  auto up = [&](size_t off, const void* src, size_t nbytes) -> hipError_t {
-    if (nbytes == 0) return hipSuccess;
-    return hipMemcpyAsync(ws + off, src, nbytes, hipMemcpyHostToDevice, c->stream);
-  };
-  HIP_TRY(c, hipMemsetAsync(ws, 0, p.lay.total, c->stream));
-  HIP_TRY(c, up(p.line_from, n->line_from, size_t(L) * 4));
-  HIP_TRY(c, up(p.line_to, n->line_to, size_t(L) * 4));
-  HIP_TRY(c, up(p.sus, n->line_sus, size_t(L) * 8));
-  HIP_TRY(c, up(p.cap, n->line_cap, size_t(L) * 8));
-  HIP_TRY(c, up(p.outage_k, outage_k.data(), size_t(Kpp) * 4));
-  HIP_TRY(c, up(p.node_lptr, lptr.data(), size_t(N + 1) * 4));
-  HIP_TRY(c, up(p.node_lterm, lterm.data(), lterm.size() * 4));
-  HIP_TRY(c, up(p.node_nptr, nptr.data(), size_t(N + 1) * 4));
-  HIP_TRY(c, up(p.node_nterm, nterm.data(), nterm.size() * 4));
-  HIP_TRY(c, up(p.deg, deg.data(), size_t(N) * 8));
-  HIP_TRY(c, up(p.nc_node, nc_node.data(), size_t(Jnc) * 4));
-  HIP_TRY(c, up(p.ramp_idx, ramp_idx.data(), size_t(G) * 4));
-  HIP_TRY(c, up(p.gen_c2, n->gen_c2, size_t(G) * 8));
-  HIP_TRY(c, up(p.gen_c1, n->gen_c1, size_t(G) * 8));
-  HIP_TRY(c, up(p.gen_pmin, n->gen_pmin, size_t(G) * T * 8));
-  HIP_TRY(c, up(p.gen_pmax, n->gen_pmax, size_t(G) * T * 8));
-  HIP_TRY(c, up(p.gen_ramp, n->gen_ramp, size_t(G) * 8));
-  HIP_TRY(c, up(p.load_d, n->load_d, size_t(D) * T * 8));
-  HIP_TRY(c, up(p.bat_P, n->bat_P, size_t(B) * 8));
-  HIP_TRY(c, up(p.bat_dur, n->bat_dur, size_t(B) * 8));
-  HIP_TRY(c, up(p.bat_eta, n->bat_eta, size_t(B) * 8));
-  HIP_TRY(c, up(p.bat_alpha, n->bat_alpha, size_t(B) * 8));
-
-  Topo& tp = c->topo;
-  tp.N = N; tp.T = T; tp.K = probe.K; tp.Kp = probe.Kp; tp.Kpp = Kpp; tp.L = L; tp.G = G;
-  tp.D = D; tp.B = B; tp.Jnc = Jnc; tp.nR = probe.nR;
-  tp.line_from = reinterpret_cast<const int32_t*>(ws + p.line_from);
-  tp.line_to = reinterpret_cast<const int32_t*>(ws + p.line_to);
-  tp.sus = reinterpret_cast<const double*>(ws + p.sus);
-  tp.cap = reinterpret_cast<const double*>(ws + p.cap);
-  tp.outage_k = reinterpret_cast<const int32_t*>(ws + p.outage_k);
-  tp.node_lptr = reinterpret_cast<const int32_t*>(ws + p.node_lptr);
-  tp.node_lterm = reinterpret_cast<const int2*>(ws + p.node_lterm);
-  tp.node_nptr = reinterpret_cast<const int32_t*>(ws + p.node_nptr);
-  tp.node_nterm = reinterpret_cast<const int32_t*>(ws + p.node_nterm);
-  tp.deg = reinterpret_cast<const double*>(ws + p.deg);
-  tp.nc_node = reinterpret_cast<const int32_t*>(ws + p.nc_node);
-  tp.ramp_idx = reinterpret_cast<const int32_t*>(ws + p.ramp_idx);
-  tp.gen_c2 = reinterpret_cast<const double*>(ws + p.gen_c2);
-  tp.gen_c1 = reinterpret_cast<const double*>(ws + p.gen_c1);
-  tp.gen_pmin = reinterpret_cast<const double*>(ws + p.gen_pmin);
-  tp.gen_pmax = reinterpret_cast<const double*>(ws + p.gen_pmax);
-  tp.gen_ramp = reinterpret_cast<const double*>(ws + p.gen_ramp);
-  tp.load_d = reinterpret_cast<const double*>(ws + p.load_d);
-  tp.bat_P = reinterpret_cast<const double*>(ws + p.bat_P);
-  tp.bat_dur = reinterpret_cast<const double*>(ws + p.bat_dur);
-  tp.bat_eta = reinterpret_cast<const double*>(ws + p.bat_eta);
-  tp.bat_alpha = reinterpret_cast<const double*>(ws + p.bat_alpha);
-
-  c->ctl = reinterpret_cast<Ctl*>(ws + p.ctl);
-  c->ring = reinterpret_cast<Rec*>(ws + p.ring);
-  auto fill_geom = [&](Geom& g, int vec, int resident) {
-    make_geom(c, vec, g);
-    if (resident >= 8) {
-      const int cap = std::min(kMaxSweepBlocks, resident / 8 * 8);
-      g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
-    }
-    g.part_sweep = reinterpret_cast<double*>(ws + p.part_sweep);
-    g.part_nc = reinterpret_cast<double*>(ws + p.part_nc);
-    g.ctl = c->ctl;
-    g.ring = c->ring;
-  };
-  fill_geom(c->geom64, 2, sweep_resident_blocks<double, double>());
-  fill_geom(c->geom32, 4, c->bf16_duals ? sweep_resident_blocks<float, bf16_t>()
-                                       : sweep_resident_blocks<float, float>());
-  c->has64 = p.has64;
-  c->has32 = p.has32;
-  if (p.has64) c->st64 = state_ptrs<double, double>(ws, p.o64);
-  if (p.has32) {
-    if (c->bf16_duals)
-      c->st32b = state_ptrs<float, bf16_t>(ws, p.o32);
-    else
-      c->st32 = state_ptrs<float, float>(ws, p.o32);
-  }
-  c->precision = p.has32 ? 1 : 0;
-  c->eps_eff = c->opt.eps * (c->opt.eps_relative ? load_rms : 1.0);
-  const double J = 2.0 * L + Jnc;
-  c->rms_norm = std::sqrt(2.0 * J * T * double(probe.Kp));
-  Ctl& h = *c->h_ctl;
-  std::memset(&h, 0, sizeof(Ctl));
-  h.rho_p = c->opt.rho_p;
-  h.rho_th = c->opt.rho_theta;
-  h.su = 1.0;
-  h.sv = 1.0;
-  h.eps_eff = c->eps_eff;
-  h.rms_norm = c->rms_norm;
-  h.mu = c->opt.mu;
-  h.gamma = c->opt.gamma;
-  h.adapt_every = c->opt.adapt_every;
-  h.check_every = c->opt.check_every;
-  h.max_iter = c->opt.max_iter;
-  h.min_iter = c->opt.min_iter;
-  h.precision = c->precision;
-  HIP_TRY(c, hipMemcpyAsync(c->ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->host_iter = 0;
-  c->loaded = true;
+opf_status opf_num_instances(opf_ctx* c, int32_t* count) {
+  if (!c || !count) return fail(c, OPF_E_INVALID, "NULL argument");
+  *count = c->loaded ? int32_t(c->inst.size()) : 0;
   return OPF_OK;
+}
+
+opf_status opf_reset(opf_ctx* c) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  return reset_state(c);
 }
 
 opf_status opf_iterate(opf_ctx* c, int32_t n) {
@@ -717,69 +985,65 @@ opf_status opf_solve(opf_ctx* c, opf_resid* out) {
   // penalty-update period
   const bool graph_ok = c->opt.use_graphs && !c->timing && c->stream != nullptr &&
                         (ae == 0 || blk % ae == 0);
-  opf_status s = read_ctl(c);
+  opf_status s = read_ctls(c);
   if (s != OPF_OK) return s;
-  while (!c->h_ctl->done && c->h_ctl->iter < c->opt.max_iter) {
-    const bool aligned = ae == 0 || c->host_iter % ae == 0;
-    if (graph_ok && aligned) {
-      const auto key = std::make_pair(c->precision, blk);
-      auto it = c->graphs.find(key);
-      if (it == c->graphs.end()) {
-        hipGraph_t gr;
-        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_n(c, blk, true, 0);
-        HIP_TRY(c, hipStreamEndCapture(c->stream, &gr));
-        hipGraphExec_t ex;
-        HIP_TRY(c, hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(gr);
-        it = c->graphs.emplace(key, ex).first;
-      }
-      HIP_TRY(c, hipGraphLaunch(it->second, c->stream));
-      c->host_iter += blk;
-    } else {
-      const int n = (graph_ok && !aligned) ? int(ae - c->host_iter % ae) : blk;
-      enqueue_n(c, n, false, c->host_iter);
-      c->host_iter += n;
-    }
-    HIP_TRY(c, hipGetLastError());
-    s = read_ctl(c);
+  bool numeric = false;
+  while (!all_done(c) && c->host_iter < int64_t(c->opt.max_iter)) {
+    s = enqueue_block(c, blk, graph_ok);
     if (s != OPF_OK) return s;
-    if (c->h_ctl->numeric_bad) break;
-    if (c->precision == 1 && c->opt.polish_fp64 && c->has64 && !c->h_ctl->done) {
+    s = read_ctls(c);
+    if (s != OPF_OK) return s;
+    for (size_t i = 0; i < c->inst.size(); ++i) numeric = numeric || c->h_ctl[i].numeric_bad;
+    if (numeric) break;
+    // FP64 polish of a single FP32 instance near the tolerance
+    if (!c->batch && c->precision == 1 && c->opt.polish_fp64 && c->has64 && !c->h_ctl[0].done) {
       opf_resid r;
-      s = last_record(c, &r);
+      s = last_record(c, 0, &r);
       if (s != OPF_OK) return s;
-      if (r.iter > 0 && std::max(r.rms_primal, r.rms_dual) <= c->opt.polish_factor * c->eps_eff) {
+      if (r.iter > 0 &&
+          std::max(r.rms_primal, r.rms_dual) <= c->opt.polish_factor * c->inst[0].eps_eff) {
         s = widen_to_fp64(c);
         if (s != OPF_OK) return s;
       }
     }
   }
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
   opf_resid r;
-  s = last_record(c, &r);
+  s = last_record(c, 0, &r);
   if (s != OPF_OK) return s;
   if (out) *out = r;
-  if (c->h_ctl->numeric_bad) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
-  return c->h_ctl->converged ? OPF_OK : OPF_NOT_CONVERGED;
-}
-
-opf_status opf_residuals(opf_ctx* c, opf_resid* out) {
-  if (!c || !out) return fail(c, OPF_E_INVALID, "NULL argument");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
-  opf_status s = last_record(c, out);
-  if (s != OPF_OK) return s;
-  if (c->h_ctl->numeric_bad) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
+  if (numeric) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
+  for (size_t i = 0; i < c->inst.size(); ++i)
+    if (!c->h_ctl[i].converged) return OPF_NOT_CONVERGED;
   return OPF_OK;
 }
 
-opf_status opf_residual_history(opf_ctx* c, opf_resid* out, int32_t max, int32_t* n) {
-  if (!c || !out || !n || max < 0) return fail(c, OPF_E_INVALID, "bad argument");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
-  opf_status s = read_ctl(c);
+opf_status opf_residuals_i(opf_ctx* c, int32_t i, opf_resid* out) {
+  opf_status s = check_inst(c, i);
   if (s != OPF_OK) return s;
-  const int iter = c->h_ctl->iter;
+  if (!out) return fail(c, OPF_E_INVALID, "out is NULL");
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  s = last_record(c, i, out);
+  if (s != OPF_OK) return s;
+  if (c->h_ctl[i].numeric_bad) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
+  return OPF_OK;
+}
+
+opf_status opf_residuals(opf_ctx* c, opf_resid* out) { return opf_residuals_i(c, 0, out); }
+
+opf_status opf_residual_history_i(opf_ctx* c, int32_t inst, opf_resid* out, int32_t max,
+                                  int32_t* n) {
+  opf_status s = check_inst(c, inst);
+  if (s != OPF_OK) return s;
+  if (!out || !n || max < 0) return fail(c, OPF_E_INVALID, "bad argument");
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  const int iter = c->h_ctl[inst].iter;
   const int ce = std::max(1, c->opt.check_every);
-  HIP_TRY(c, hipMemcpyAsync(c->h_rec, c->ring, sizeof(Rec) * kRing, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_rec, c->inst[inst].ring, sizeof(Rec) * kRing,
+                            hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const int first = std::max(1, iter - kRing + 1);
   int cnt = 0;
@@ -788,53 +1052,57 @@ opf_status opf_residual_history(opf_ctx* c, opf_resid* out, int32_t max, int32_t
     const Rec& r = c->h_rec[(i - 1) % kRing];
     opf_resid& o = out[cnt++];
     std::memset(&o, 0, sizeof(o));
+    fill_resid(r, &o);
     o.iter = r.iter;
-    o.primal_p = r.primal_p;
-    o.primal_theta = r.primal_th;
-    o.dual_p = r.dual_p;
-    o.dual_theta = r.dual_th;
-    o.rms_primal = r.rms_primal;
-    o.rms_dual = r.rms_dual;
-    o.threshold = r.threshold;
-    o.objective = r.objective;
-    o.rho_p = r.rho_p;
-    o.rho_theta = r.rho_th;
-    o.converged = r.converged;
-    o.precision = r.precision == 0 ? OPF_F64 : OPF_F32;
   }
   *n = cnt;
   return OPF_OK;
 }
 
-opf_status opf_field_size(opf_ctx* c, int32_t field, size_t* count) {
-  if (!c || !count) return fail(c, OPF_E_INVALID, "NULL argument");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
-  const size_t KT = size_t(c->Kp) * c->T;
+opf_status opf_residual_history(opf_ctx* c, opf_resid* out, int32_t max, int32_t* n) {
+  return opf_residual_history_i(c, 0, out, max, n);
+}
+
+opf_status opf_field_size_i(opf_ctx* c, int32_t inst, int32_t field, size_t* count) {
+  opf_status s = check_inst(c, inst);
+  if (s != OPF_OK) return s;
+  if (!count) return fail(c, OPF_E_INVALID, "NULL argument");
+  const Inst& x = c->inst[inst];
+  const size_t KT = size_t(x.Kp) * x.T;
   if (field >= OPF_FIELD_P && field <= OPF_FIELD_V2)
-    *count = KT * c->L;
+    *count = KT * x.L;
   else if (field >= OPF_FIELD_U && field <= OPF_FIELD_THBAR)
-    *count = KT * c->N;
+    *count = KT * x.N;
   else if (field >= OPF_FIELD_PNC && field <= OPF_FIELD_VNC)
-    *count = size_t(c->Jnc) * c->T;
+    *count = size_t(x.Jnc) * x.T;
   else
     return fail(c, OPF_E_INVALID, "unknown field");
   return OPF_OK;
 }
 
-opf_status opf_get_field(opf_ctx* c, int32_t field, double* dst, size_t count) {
+opf_status opf_field_size(opf_ctx* c, int32_t field, size_t* count) {
+  return opf_field_size_i(c, 0, field, count);
+}
+
+opf_status opf_get_field_i(opf_ctx* c, int32_t inst, int32_t field, double* dst, size_t count) {
   size_t need = 0;
-  opf_status s = opf_field_size(c, field, &need);
+  opf_status s = opf_field_size_i(c, inst, field, &need);
   if (s != OPF_OK) return s;
   if (!dst) return fail(c, OPF_E_INVALID, "dst is NULL");
   if (count < need) return fail(c, OPF_E_INVALID, "dst too small: need " + std::to_string(need));
+  const Inst& x = c->inst[inst];
   if (c->precision == 0)
-    launch_export(kargs(c, c->st64, c->geom64), field, dst, c->stream);
+    launch_export(kargs(x, x.st64, x.geom64), field, dst, c->stream);
   else if (c->bf16_duals)
-    launch_export(kargs(c, c->st32b, c->geom32), field, dst, c->stream);
+    launch_export(kargs(x, x.st32b, x.geom32), field, dst, c->stream);
   else
-    launch_export(kargs(c, c->st32, c->geom32), field, dst, c->stream);
+    launch_export(kargs(x, x.st32, x.geom32), field, dst, c->stream);
   HIP_TRY(c, hipGetLastError());
   return OPF_OK;
+}
+
+opf_status opf_get_field(opf_ctx* c, int32_t field, double* dst, size_t count) {
+  return opf_get_field_i(c, 0, field, dst, count);
 }
 
 opf_status opf_set_timing(opf_ctx* c, int32_t enable) {
@@ -878,26 +1146,115 @@ opf_status opf_kernel_bytes(opf_ctx* c, int32_t kernel, double* bytes) {
   if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
   const double S = c->precision == 0 ? 8.0 : 4.0;
   const double SV = c->precision == 0 ? 8.0 : (c->bf16_duals ? 2.0 : 4.0);
-  const double KT = double(c->Kp) * c->T;
-  const double L = c->L, N = c->N;
-  const double J = double(c->Jnc) * c->T;
-  switch (kernel) {
-    case OPF_KERNEL_DEVICES:
-      // per device and period: read p, theta, averaged dual, both node
-      // averages and a parameter; write p, theta, averaged dual
-      *bytes = J * 9.0 * S;
-      break;
-    case OPF_KERNEL_SWEEP:
-      // per (k, l, t): read and write P, Tm (S each) and V1, V2 (SV each);
-      // per (k, n, t): read and write U, W, thetabar
-      *bytes = KT * (L * 2.0 * (2.0 * S + 2.0 * SV) + N * 6.0 * S);
-      break;
-    case OPF_KERNEL_RESCALE:
-      *bytes = KT * N * 4.0 * S;
-      break;
-    default:
-      *bytes = 0.0;
+  double total = 0.0;
+  for (const Inst& x : c->inst) {
+    const double KT = double(x.Kp) * x.T;
+    const double L = x.L, N = x.N;
+    const double J = double(x.Jnc) * x.T;
+    switch (kernel) {
+      case OPF_KERNEL_DEVICES:
+        // per device and period: read p, theta, averaged dual, both node
+        // averages and a parameter; write p, theta, averaged dual
+        total += J * 9.0 * S;
+        break;
+      case OPF_KERNEL_SWEEP:
+        // per (k, l, t): read and write P, Tm (S each) and V1, V2 (SV each);
+        // per (k, n, t): read and write U, W, thetabar
+        total += KT * (L * 2.0 * (2.0 * S + 2.0 * SV) + N * 6.0 * S);
+        break;
+      case OPF_KERNEL_RESCALE:
+        total += KT * N * 4.0 * S;
+        break;
+      default:
+        break;
+    }
   }
+  *bytes = total;
+  return OPF_OK;
+}
+
+opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_tuning* out) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (trials < 1) return fail(c, OPF_E_INVALID, "trials must be >= 1");
+  // cache key: device, precision, shape of the loaded instances
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  HIP_TRY(c, hipGetDeviceProperties(&prop, dev));
+  int64_t sN = 0, sL = 0, sKT = 0;
+  for (const Inst& x : c->inst) {
+    sN += int64_t(x.N) * x.T;
+    sL += int64_t(x.L) * x.T;
+    sKT += int64_t(x.Kp) * x.T;
+  }
+  std::ostringstream key;
+  key << prop.gcnArchName << "|p" << c->precision << (c->bf16_duals ? "b" : "") << "|n"
+      << c->inst.size() << "|NT" << sN << "|LT" << sL << "|KT" << sKT;
+  opf_tuning best{};
+  best.ms_per_iter = 1e300;
+  bool cached = false;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string k;
+    int shift;
+    double gf, ms;
+    while (in >> k >> shift >> gf >> ms)
+      if (k == key.str()) {
+        best.lanes_shift = shift;
+        best.grid_factor = gf;
+        best.ms_per_iter = ms;
+        cached = true;
+      }
+  }
+  if (!cached) {
+    const bool timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    for (int shift = -1; shift <= 1; ++shift) {
+      for (double gf : {0.5, 1.0, 2.0}) {
+        c->lanes_shift = shift;
+        c->grid_factor = gf;
+        opf_status s = refresh_geometry(c);
+        if (s != OPF_OK) return s;
+        s = reset_state(c);
+        if (s != OPF_OK) return s;
+        enqueue_n(c, 2, false, c->host_iter);  // warm-up
+        c->host_iter += 2;
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        enqueue_n(c, trials, false, c->host_iter);
+        c->host_iter += trials;
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        const double per = double(ms) / trials;
+        if (per < best.ms_per_iter) {
+          best.ms_per_iter = per;
+          best.lanes_shift = shift;
+          best.grid_factor = gf;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    if (cache_path) {
+      std::ofstream outf(cache_path, std::ios::app);
+      outf << key.str() << " " << best.lanes_shift << " " << best.grid_factor << " "
+           << best.ms_per_iter << "\n";
+    }
+  }
+  c->lanes_shift = best.lanes_shift;
+  c->grid_factor = best.grid_factor;
+  opf_status s = refresh_geometry(c);
+  if (s != OPF_OK) return s;
+  s = reset_state(c);
+  if (s != OPF_OK) return s;
+  best.from_cache = cached ? 1 : 0;
+  if (out) *out = best;
   return OPF_OK;
 }
 

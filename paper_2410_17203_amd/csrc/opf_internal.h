@@ -133,6 +133,19 @@ struct KArgs {
   Geom g;
 };
 
+// Work list of a batch: device-resident descriptors of every instance (an
+// array of KArgs of the active precision) and prefix sums of the per-instance
+// device waves and sweep row groups.
+struct BatchTab {
+  const void* descs;
+  const int64_t* dev_prefix;  // [n_inst + 1]
+  const int64_t* grp_prefix;  // [n_inst + 1]
+  int32_t n_inst;
+  int32_t n_sweep_blocks;
+  int64_t total_dev;
+  int64_t total_grps;
+};
+
 // Host-side launchers (opf_kernels.hip).
 template <typename R, typename VT>
 int sweep_resident_blocks();
@@ -146,6 +159,16 @@ template <typename R, typename VT>
 void launch_rescale(const KArgs<R, VT>& a, hipStream_t s);
 template <typename R, typename VT>
 void launch_export(const KArgs<R, VT>& a, int field, double* dst, hipStream_t s);
+template <typename R, typename VT>
+void launch_batch_iter_devices(const BatchTab& tab, int max_T, hipStream_t s);
+template <typename R, typename VT>
+void launch_batch_iter_sweep(const BatchTab& tab, hipStream_t s);
+template <typename R, typename VT>
+void launch_batch_iter_finalize(const BatchTab& tab, hipStream_t s);
+template <typename R, typename VT>
+void launch_batch_iter_rescale(const BatchTab& tab, hipStream_t s);
+template <typename R, typename VT>
+int sweep_batch_resident_blocks();
 // Widening copy of a FP32 iterate into a FP64 iterate (polishing).
 template <typename VT>
 void launch_widen(const KArgs<float, VT>& src, const KArgs<double, double>& dst, hipStream_t s);

@@ -783,8 +783,10 @@ __device__ inline double adapt_rule(double rho, double rpri, double rdual, doubl
   return rho;
 }
 
+// Residual norms, stopping test and adaptive penalty of one instance, run by
+// one block.  Partials: n_sweep entries of 5 sums, n_nc entries of 2.
 template <typename R, typename VT>
-__global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
+__device__ void finalize_body(const KArgs<R, VT>& a, int n_sweep, int n_nc) {
   Ctl* ctl = a.g.ctl;
   __shared__ double sh[kBlock / kWave];
   __shared__ int sdone;
@@ -798,10 +800,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
   const bool check = (iter % ctl->check_every) == 0;
   double s[7] = {0, 0, 0, 0, 0, 0, 0};  // 5 sweep partials, device dual, objective
   if (check) {
-    for (int i = threadIdx.x; i < a.g.n_sweep_blocks; i += kBlock)
+    for (int i = threadIdx.x; i < n_sweep; i += kBlock)
 #pragma unroll
       for (int k = 0; k < 5; ++k) s[k] += a.g.part_sweep[5 * i + k];
-    for (int i = threadIdx.x; i < a.g.n_nc_blocks; i += kBlock) {
+    for (int i = threadIdx.x; i < n_nc; i += kBlock) {
       s[5] += a.g.part_nc[2 * i];
       s[6] += a.g.part_nc[2 * i + 1];
     }
@@ -854,48 +856,174 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
   if (conv || bad || iter >= ctl->max_iter) ctl->done = 1;
 }
 
-// u <- su u after a penalty change (current buffer, same row mapping as the
-// sweep).
 template <typename R, typename VT>
-__global__ void __launch_bounds__(kBlock) k_rescale(KArgs<R, VT> a) {
+__global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
+  finalize_body(a, a.g.n_sweep_blocks, a.g.n_nc_blocks);
+}
+
+// u <- su u after a penalty change for one (period, node) row of the current
+// buffer (lane group of lanes_per_row lanes).
+template <typename R, typename VT>
+__device__ inline void rescale_row(const KArgs<R, VT>& a, const Buf<R, VT>& C, R su, int64_t row,
+                                   int q, int lpr) {
   constexpr int VEC = 16 / sizeof(R);
   using VR = Vec<R, VEC>;
+  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  const bool act = row < NT;
+  R sumw = R(0);
+  if (act) {
+    for (int v = q; v < a.g.nv; v += lpr) {
+      const size_t off = size_t(row) * a.tp.Kpp + v * VEC;
+      const VR U = *reinterpret_cast<const VR*>(C.U + off);
+      const VR W = *reinterpret_cast<const VR*>(C.W + off);
+      VR Un, Wn;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        Un.x[e] = su * U.x[e];
+        Wn.x[e] = W.x[e] + (su - R(1)) * U.x[e];
+        sumw += Wn.x[e];
+      }
+      *reinterpret_cast<VR*>(C.U + off) = Un;
+      *reinterpret_cast<VR*>(C.W + off) = Wn;
+    }
+  }
+  for (int d = lpr >> 1; d > 0; d >>= 1) sumw += __shfl_xor(sumw, d);
+  if (act && q == 0) {
+    const int t = int(row / a.tp.N), n = int(row - int64_t(t) * a.tp.N);
+    a.st.avgW[size_t(n) * a.tp.T + t] = sumw / R(a.tp.Kp);
+  }
+}
+
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_rescale(KArgs<R, VT> a) {
   Ctl* ctl = a.g.ctl;
   if (ctl->scale_iter != ctl->launches) return;
   const R su = R(ctl->su);
   if (su == R(1)) return;
   const Buf<R, VT> C = a.st.buf[ctl->cur];
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, a.g.n_grps);
-  const int nv = a.g.nv, lpr = a.g.lanes_per_row;
+  const int lpr = a.g.lanes_per_row;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int rw = lane / lpr, q = lane - rw * lpr;
   const int rows_per_wave = kWave / lpr;
-  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step)
+    rescale_row(a, C, su, (gi * (kBlock / kWave) + w) * rows_per_wave + rw, q, lpr);
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution: many instances of uneven size, one launch per phase over
+// a work list spanning all of them.  Each instance keeps its own control
+// block (penalties, counters, convergence) and buffers; finished instances
+// are skipped.  Residual partials are written per (row group, wave) and per
+// device, so no block-wide barrier is needed inside the work loops.
+
+__device__ inline int find_inst(const int64_t* prefix, int n, int64_t g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename R, typename VT, int E>
+__global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
+  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t gw = int64_t(blockIdx.x) * (kBlock / kWave) + w;
+  if (gw >= tab.total_dev) return;
+  const int i = find_inst(tab.dev_prefix, tab.n_inst, gw);
+  const KArgs<R, VT>& a = descs[i];
+  Ctl* ctl = a.g.ctl;
+  if (ctl->done) return;
+  const int j = int(gw - tab.dev_prefix[i]);
+  const R rp = R(ctl->rho_p), su = R(ctl->su), sv = R(ctl->sv);
+  double dp = 0.0, ob = 0.0;
+  nc_device<R, VT, E>(a, j, lane, su, sv, R(a.tp.Kp) * rp, dp, ob);
+  dp = wave_sum(dp);
+  ob = wave_sum(ob);
+  if (lane == 0) {
+    a.g.part_nc[2 * j] = dp;
+    a.g.part_nc[2 * j + 1] = ob;
+  }
+}
+
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
+  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
-    const int64_t row = (gi * (kBlock / kWave) + w) * rows_per_wave + rw;
+    const int i = find_inst(tab.grp_prefix, tab.n_inst, gi);
+    const KArgs<R, VT>& a = descs[i];
+    Ctl* ctl = a.g.ctl;
+    if (ctl->done) continue;
+    const int cur = ctl->cur;
+    const Buf<R, VT> A = a.st.buf[cur];
+    const Buf<R, VT> B = a.st.buf[cur ^ 1];
+    const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
+    const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
+    const int64_t li = gi - tab.grp_prefix[i];
+    const int nv = a.g.nv, lpr = a.g.lanes_per_row;
+    const int rw = lane / lpr, q = lane - rw * lpr;
+    const int64_t row = (li * (kBlock / kWave) + w) * (kWave / lpr) + rw;
+    const int64_t NT = int64_t(a.tp.N) * a.tp.T;
     const bool act = row < NT;
-    R sumw = R(0);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    R sumw = R(0), sumb = R(0);
     if (act) {
-      for (int v = q; v < nv; v += lpr) {
-        const size_t off = size_t(row) * a.tp.Kpp + v * VEC;
-        const VR U = *reinterpret_cast<const VR*>(C.U + off);
-        const VR W = *reinterpret_cast<const VR*>(C.W + off);
-        VR Un, Wn;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          Un.x[e] = su * U.x[e];
-          Wn.x[e] = W.x[e] + (su - R(1)) * U.x[e];
-          sumw += Wn.x[e];
-        }
-        *reinterpret_cast<VR*>(C.U + off) = Un;
-        *reinterpret_cast<VR*>(C.W + off) = Wn;
-      }
+      const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
+      const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
+      for (int v = q; v < nv; v += lpr)
+        sweep_vec<R, VT>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
-    for (int d = lpr >> 1; d > 0; d >>= 1) sumw += __shfl_xor(sumw, d);
+    for (int d = lpr >> 1; d > 0; d >>= 1) {
+      sumw += __shfl_xor(sumw, d);
+      sumb += __shfl_xor(sumb, d);
+    }
     if (act && q == 0) {
       const int t = int(row / a.tp.N), n = int(row - int64_t(t) * a.tp.N);
       a.st.avgW[size_t(n) * a.tp.T + t] = sumw / R(a.tp.Kp);
+      a.st.avgTB[size_t(n) * a.tp.T + t] = sumb / R(a.tp.Kp);
     }
+    if (check) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) a.g.part_sweep[5 * (li * (kBlock / kWave) + w) + k] = s;
+      }
+    }
+  }
+}
+
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
+  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const KArgs<R, VT>& a = descs[blockIdx.x];
+  const int64_t ng = tab.grp_prefix[blockIdx.x + 1] - tab.grp_prefix[blockIdx.x];
+  finalize_body(a, int(ng * (kBlock / kWave)), a.tp.Jnc);
+}
+
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_rescale_batch(BatchTab tab) {
+  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
+    const int i = find_inst(tab.grp_prefix, tab.n_inst, gi);
+    const KArgs<R, VT>& a = descs[i];
+    Ctl* ctl = a.g.ctl;
+    if (ctl->scale_iter != ctl->launches) continue;
+    const R su = R(ctl->su);
+    if (su == R(1)) continue;
+    const int lpr = a.g.lanes_per_row;
+    const int rw = lane / lpr, q = lane - rw * lpr;
+    const int64_t li = gi - tab.grp_prefix[i];
+    rescale_row(a, a.st.buf[ctl->cur], su, (li * (kBlock / kWave) + w) * (kWave / lpr) + rw, q,
+                lpr);
   }
 }
 
@@ -1051,7 +1179,50 @@ void launch_widen(const KArgs<float, VT>& a, const KArgs<double, double>& b, hip
   widen(a.st.bat_st, b.st.bat_st, 6 * int64_t(tp.B) * tp.T, s);
 }
 
+template <typename R, typename VT>
+void launch_batch_iter_devices(const BatchTab& tab, int max_T, hipStream_t s) {
+  const int64_t grid = (tab.total_dev + (kBlock / kWave) - 1) / (kBlock / kWave);
+  if (grid == 0) return;
+  const int E = (max_T + kWave - 1) / kWave;
+  switch (E) {
+    case 1: k_devices_batch<R, VT, 1><<<dim3(unsigned(grid)), kBlock, 0, s>>>(tab); break;
+    case 2: k_devices_batch<R, VT, 2><<<dim3(unsigned(grid)), kBlock, 0, s>>>(tab); break;
+    case 3: k_devices_batch<R, VT, 3><<<dim3(unsigned(grid)), kBlock, 0, s>>>(tab); break;
+    default: k_devices_batch<R, VT, 4><<<dim3(unsigned(grid)), kBlock, 0, s>>>(tab); break;
+  }
+}
+
+template <typename R, typename VT>
+void launch_batch_iter_sweep(const BatchTab& tab, hipStream_t s) {
+  k_sweep_batch<R, VT><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
+}
+
+template <typename R, typename VT>
+void launch_batch_iter_finalize(const BatchTab& tab, hipStream_t s) {
+  k_finalize_batch<R, VT><<<tab.n_inst, kBlock, 0, s>>>(tab);
+}
+
+template <typename R, typename VT>
+void launch_batch_iter_rescale(const BatchTab& tab, hipStream_t s) {
+  k_rescale_batch<R, VT><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
+}
+
+template <typename R, typename VT>
+int sweep_batch_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_batch<R, VT>, kBlock, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
 #define OPF_INSTANTIATE(R, VT)                                                       \
+  template void launch_batch_iter_devices<R, VT>(const BatchTab&, int, hipStream_t); \
+  template void launch_batch_iter_sweep<R, VT>(const BatchTab&, hipStream_t);        \
+  template void launch_batch_iter_finalize<R, VT>(const BatchTab&, hipStream_t);     \
+  template void launch_batch_iter_rescale<R, VT>(const BatchTab&, hipStream_t);      \
+  template int sweep_batch_resident_blocks<R, VT>();                                 \
   template int sweep_resident_blocks<R, VT>();                                       \
   template void launch_devices<R, VT>(const KArgs<R, VT>&, hipStream_t);            \
   template void launch_sweep<R, VT>(const KArgs<R, VT>&, hipStream_t);              \

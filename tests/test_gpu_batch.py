@@ -1,0 +1,156 @@
+"""Batched uneven instances: every phase is one launch over all instances.
+
+Each instance of a batch must give the iterates it gives alone (and the
+oracle's), keep its own penalty sequence and convergence, and the autotuner
+must leave the iterate at the zero start.
+"""
+import functools
+import math
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.mp import Options, Solver as Oracle
+from paper_2410_17203_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["P", "TH1", "TH2", "V1", "V2", "U", "PBAR", "THBAR", "PNC", "THNC", "VNC"]
+
+SHAPES = [  # N, T, K: uneven horizon, contingency count and size
+    (30, 1, 0), (80, 24, 5), (120, 24, 12), (60, 48, 30), (200, 1, 3), (20, 48, 7),
+]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def batch_instances():
+    out = []
+    for i, (N, T, K) in enumerate(SHAPES):
+        out.append(synth.make_instance(f"b{i}", N=N, L=int(round(1.4 * N)), G=max(2, N // 5),
+                                       D=int(0.8 * N), B=max(1, N // 25), T=T, K=K,
+                                       seed=900 + i))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_state(i, iters):
+    o = Oracle(batch_instances()[i], Options(adapt_every=0, eps=1e-12))
+    o.run(iters)
+    return o.canonical_state()
+
+
+def rel_err(a, b):
+    nb = float(torch.linalg.norm(b))
+    na = float(torch.linalg.norm(a - b))
+    return na if nb == 0.0 else na / nb
+
+
+def test_batched_iterates_match_oracle_per_instance():
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] fp64 vs oracle")
+    insts = batch_instances()
+    s = Solver(insts, dtype="f64", adapt_every=0, eps=1e-12)
+    assert s.num_instances == len(insts)
+    s.iterate(150)
+    for i in range(len(insts)):
+        ref = oracle_state(i, 150)
+        errs = {f: rel_err(s.field(f, i), ref[f]) for f in FIELDS}
+        bad = {k: v for k, v in errs.items() if not v <= 1e-10}
+        assert not bad, (i, bad)
+        assert s.residuals(i)["iter"] == 150
+    s.close()
+
+
+def test_batched_equals_one_at_a_time():
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] batched vs single, adaptive penalty")
+    insts = batch_instances()
+    b = Solver(insts, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0)
+    b.iterate(120)
+    for i, inst in enumerate(insts):
+        a = Solver(inst, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0)
+        a.iterate(120)
+        ha, hb = a.history(), b.history(instance=i)
+        assert [(h["rho_p"], h["rho_theta"]) for h in ha] == \
+            [(h["rho_p"], h["rho_theta"]) for h in hb]
+        for f in ["P", "TH1", "U", "THBAR", "PNC"]:
+            assert rel_err(b.field(f, i), a.field(f)) <= 1e-12, (i, f)
+        a.close()
+    b.close()
+
+
+def test_batched_solve_stops_each_instance_on_its_own():
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] solve fp32")
+    insts = batch_instances()
+    cap = 6000
+    b = Solver(insts, dtype="f32", eps=1e-3, max_iter=cap)
+    r = b.solve()
+    res = [b.residuals(i) for i in range(len(insts))]
+    conv = [x["converged"] for x in res]
+    assert r["status"] == ("OPF_OK" if all(conv) else "OPF_NOT_CONVERGED")
+    # the single-period instances converge early, at different iterations
+    done = [x["iter"] for x in res if x["converged"]]
+    assert len(done) >= 2 and len(set(done)) == len(done)
+    for x in res:
+        if x["converged"]:
+            assert x["iter"] < cap
+            assert max(x["rms_primal"], x["rms_dual"]) <= x["threshold"]
+        else:
+            assert x["iter"] == cap
+    # stopped instances (converged or at the cap) stay where they stopped
+    b.iterate(100)
+    for i, x in enumerate(res):
+        assert b.residuals(i)["iter"] == x["iter"]
+    # each instance stops where its own single-instance solve stops
+    for i, inst in enumerate(insts):
+        a = Solver(inst, dtype="f32", eps=1e-3, max_iter=cap, polish_fp64=0)
+        ra = a.solve()
+        assert ra["iter"] == res[i]["iter"] and ra["converged"] == res[i]["converged"]
+        assert abs(ra["objective"] - res[i]["objective"]) <= 1e-5 * abs(ra["objective"])
+        a.close()
+    b.close()
+
+
+def test_autotune_resets_and_caches():
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] autotune")
+    insts = batch_instances()
+    b = Solver(insts, dtype="f64", adapt_every=0, eps=1e-12)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        t1 = b.autotune(trials=3, cache_path=path)
+        assert t1["from_cache"] == 0 and t1["ms_per_iter"] > 0
+        assert t1["lanes_shift"] in (-1, 0, 1) and t1["grid_factor"] in (0.5, 1.0, 2.0)
+        t2 = b.autotune(trials=3, cache_path=path)
+        assert t2["from_cache"] == 1 and t2["lanes_shift"] == t1["lanes_shift"]
+    assert b.residuals(0)["iter"] == 0  # back at the zero start
+    b.iterate(150)
+    for i in [1, 3]:
+        ref = oracle_state(i, 150)
+        for f in ["P", "U", "PNC", "VNC"]:
+            assert rel_err(b.field(f, i), ref[f]) <= 1e-10, (i, f)
+    b.close()
+
+
+def test_batched_bf16_duals_run():
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] bf16 duals")
+    insts = batch_instances()
+    b = Solver(insts, dtype="f32", dual_dtype="bf16", adapt_every=0, eps=1e-12)
+    b.iterate(150)
+    for i in range(len(insts)):
+        r = b.residuals(i)
+        assert math.isfinite(r["rms_primal"]) and math.isfinite(r["rms_dual"])
+    err = rel_err(b.field("P", 2), oracle_state(2, 150)["P"])
+    say(f"  bf16 relative error of P (instance 2) vs oracle: {err:.2e}")
+    assert err < 5e-2
+    b.close()

@@ -151,7 +151,9 @@ def test_fp32_solve_with_fp64_polish_reaches_tolerance():
     say("[solve f32+polish] tiny")
     inst = make("tiny")
     from paper_2410_17203_amd.binding import Solver
-    s = Solver(inst, dtype="f32", eps=1e-6, max_iter=20000)
+    # near 1e-6 the FP32 residual is noise around the threshold, so switch
+    # to FP64 an order of magnitude above it
+    s = Solver(inst, dtype="f32", eps=1e-6, max_iter=20000, polish_factor=10.0)
     rg = s.solve()
     assert rg["status"] == "OPF_OK"
     assert rg["precision"] == 0  # finished in FP64
