@@ -67,6 +67,38 @@ def time_iterations(solver, steps, warmup):
     return t1 - t0, kt
 
 
+def batched_rates(iters, dtype, dual_dtype):
+    """Aggregate instance-iterations/s of the 64 uneven instances as one batch
+    and solved one at a time, both in 50-iteration graph blocks."""
+    import torch
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import Solver
+    insts = synth.batched()
+    opts = dict(dtype=dtype, dual_dtype=dual_dtype, polish_fp64=0, eps=0.0, max_iter=iters)
+
+    def run(arg):
+        s = Solver(arg, **opts)
+        s.solve()  # warm-up: builds the graphs
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        return dt
+
+    t_batch = run(insts)
+    t_single = sum(run(i) for i in insts)
+    n = len(insts)
+    elems = sum((13 * i.L + 2 * (i.G + i.D + i.B) + 6 * i.N) * (i.K + 1) * i.T for i in insts)
+    return {"instances": n, "iters": iters, "state_dtype": dtype, "dual_dtype": dual_dtype,
+            "batched_inst_iters_per_s": n * iters / t_batch,
+            "one_at_a_time_inst_iters_per_s": n * iters / t_single,
+            "speedup": t_single / t_batch,
+            "algorithmic_elements_per_iteration": elems}
+
+
 def cpu_baseline(inst_name, sample_k, iters):
     """FP64 oracle on the host: the Large grid with sample_k contingencies,
     per-iteration time scaled linearly to the full K + 1."""
@@ -89,6 +121,86 @@ def cpu_baseline(inst_name, sample_k, iters):
                        f"{dt:.3f} s/iteration scaled by (K+1) ratio {scale:.1f}")}
 
 
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(directory, *suffixes):
+    for suffix in suffixes:
+        for root, _, files in os.walk(directory):
+            for f in sorted(files):
+                if f.endswith(suffix):
+                    return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffixes} under {directory}")
+
+
+def _stats_rows(directory):
+    """Per-kernel statistics: rocprofv3's own --stats table when present,
+    else the same figures computed from its kernel trace."""
+    try:
+        return _read_csv(_find(directory, "kernel_stats.csv"))
+    except FileNotFoundError:
+        pass
+    by = {}
+    for r in _read_csv(_find(directory, "kernel_trace.csv")):
+        by.setdefault(r["Kernel_Name"], []).append(
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in by.values())
+    rows = [{"Name": k, "Calls": len(v), "AverageNs": sum(v) / len(v), "MinNs": min(v),
+             "MaxNs": max(v), "Percentage": 100.0 * sum(v) / total} for k, v in by.items()]
+    return sorted(rows, key=lambda r: -r["Percentage"])
+
+
+def summarize_stats(directory, out_path, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run."""
+    rows = _stats_rows(directory)
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f}% |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_write):
+    """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the counter reads for a plain 1 GiB -> 1 GiB
+    elementwise copy in the same run."""
+    def per_kernel(directory, counter):
+        rows = [r for r in _read_csv(_find(directory, "counter_collection.csv",
+                                           "counter_collection_trace.csv"))
+                if r["Counter_Name"] == counter]
+        copy = [float(r["Counter_Value"]) for r in rows if "MulFunctor" in r["Kernel_Name"]]
+        sweep = [float(r["Counter_Value"]) for r in rows if "k_sweep<" in r["Kernel_Name"]]
+        if not copy or not sweep:
+            raise RuntimeError(f"{counter}: copy or sweep dispatches missing")
+        copy_kib = sum(copy) / len(copy)
+        factor = 2.0**20 / copy_kib  # the copy moves exactly 1 GiB each way
+        return factor, copy_kib, sum(sweep) / len(sweep), len(sweep)
+    fr, fcopy, fsweep, nf = per_kernel(fetch_dir, "FETCH_SIZE")
+    wr, wcopy, wsweep, nw = per_kernel(write_dir, "WRITE_SIZE")
+    read_b = fsweep * 1024 * fr
+    write_b = wsweep * 1024 * wr
+    d = {"kernel": "k_sweep", "workload": "large, FP32 iterate",
+         "kernel_source_hash": kernel_source_hash(),
+         "fetch_kib_per_launch_raw": fsweep, "write_kib_per_launch_raw": wsweep,
+         "copy_fetch_kib_raw": fcopy, "copy_write_kib_raw": wcopy,
+         "fetch_scale": fr, "write_scale": wr, "launches": [nf, nw],
+         "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+         "hbm_bytes_per_launch": read_b + write_b,
+         "command_fetch": command_fetch, "command_write": command_write}
+    with open(out_path, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(d, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,13 +211,28 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=50, help="0 skips the FP64 rate")
     ap.add_argument("--ttt", type=int, default=1, help="1: measure time to tolerance")
     ap.add_argument("--ttt-max-iter", type=int, default=10000)
+    ap.add_argument("--batched", type=int, default=1,
+                    help="1: also time the 64-instance batch against one-at-a-time solves")
+    ap.add_argument("--batched-iters", type=int, default=200)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-k", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="1: first run a plain 1 GiB -> 1 GiB copy kernel three times "
                          "(reference for the HBM byte counters)")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "OUT", "COMMAND"),
+                    help="host only: summarise a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-traffic", nargs=5,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "CMD_FETCH", "CMD_WRITE"),
+                    help="host only: HBM bytes per sweep launch from two --pmc runs, then exit")
     args = ap.parse_args()
+
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -180,6 +307,14 @@ def main():
         s.close()
         del s
         torch.cuda.empty_cache()
+
+    if args.batched:
+        extra["batched"] = [batched_rates(args.batched_iters, "f32", "f32"),
+                            batched_rates(args.batched_iters, "f32", "bf16")]
+        for b in extra["batched"]:
+            log(f"[bench] batch of {b['instances']} ({b['dual_dtype']} duals): "
+                f"{b['batched_inst_iters_per_s']:.0f} vs {b['one_at_a_time_inst_iters_per_s']:.0f} "
+                f"instance-iterations/s one at a time")
 
     khash = kernel_source_hash()
     out = {
