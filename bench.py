@@ -32,7 +32,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ["opf_kernels.hip", "opf_internal.h"]:
+    for f in ["opf_kernels.hip", "opf_device.h", "opf_internal.h"]:
         with open(os.path.join(ROOT, "paper_2410_17203_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,6 +97,42 @@ def batched_rates(iters, dtype, dual_dtype):
             "one_at_a_time_inst_iters_per_s": n * iters / t_single,
             "speedup": t_single / t_batch,
             "algorithmic_elements_per_iteration": elems}
+
+
+def adjoint_times(n_iters, every, dtype):
+    """Wall-clock of the recorded forward run and of the adjoint on the
+    differentiation workload (gradient of cost + <w, dispatch> w.r.t. load,
+    line capacity and generator limits)."""
+    import numpy as np
+    import torch
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import Solver
+    inst = synth.config("diff")
+    J = len(inst.gen_node) + len(inst.load_node) + len(inst.bat_node)
+    w = np.random.default_rng(2024).normal(size=(J, inst.T))
+    s = Solver(inst, dtype=dtype, polish_fp64=0)
+    s.tape_forward(50, every)  # warm-up
+    s.adjoint(w, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.tape_forward(n_iters, every)
+    t1 = time.perf_counter()
+    s.adjoint(w, 1.0)
+    t2 = time.perf_counter()
+    plain = Solver(inst, dtype=dtype, polish_fp64=0, eps=0.0, min_iter=2**31 - 1,
+                   max_iter=2**31 - 1)
+    plain.iterate(20)
+    plain.synchronize()
+    t3 = time.perf_counter()
+    plain.iterate(n_iters)
+    plain.synchronize()
+    t4 = time.perf_counter()
+    s.close()
+    plain.close()
+    return {"workload": "diff: N=500 L=700 G=100 D=400 B=20 T=24 K=20 (synthetic, seed 2024)",
+            "dtype": dtype, "iters": n_iters, "checkpoint_every": every,
+            "forward_plain_s": t4 - t3, "forward_recorded_s": t1 - t0, "backward_s": t2 - t1,
+            "backward_over_forward": (t2 - t1) / (t4 - t3)}
 
 
 def cpu_baseline(inst_name, sample_k, iters):
@@ -214,6 +250,8 @@ def main():
     ap.add_argument("--batched", type=int, default=1,
                     help="1: also time the 64-instance batch against one-at-a-time solves")
     ap.add_argument("--batched-iters", type=int, default=200)
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="1: also time 1000 unrolled iterations forward + adjoint (diff workload)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-k", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=10)
@@ -315,6 +353,12 @@ def main():
             log(f"[bench] batch of {b['instances']} ({b['dual_dtype']} duals): "
                 f"{b['batched_inst_iters_per_s']:.0f} vs {b['one_at_a_time_inst_iters_per_s']:.0f} "
                 f"instance-iterations/s one at a time")
+
+    if args.adjoint:
+        extra["adjoint"] = [adjoint_times(1000, 50, "f32"), adjoint_times(1000, 50, "f64")]
+        for a in extra["adjoint"]:
+            log(f"[bench] adjoint {a['dtype']}: forward {a['forward_plain_s']:.3f}s "
+                f"(recorded {a['forward_recorded_s']:.3f}s), backward {a['backward_s']:.3f}s")
 
     khash = kernel_source_hash()
     out = {

@@ -238,6 +238,81 @@ typedef struct {
  * measured, and new results are appended to it.  Synchronises. */
 opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, opf_tuning* out);
 
+/* ---- The iterate: layout, export and import (warm start, Section 3.4) ------ */
+
+/* Where the current iterate of one instance lives in the workspace (byte
+ * offsets from the workspace start; valid until the next iteration, which
+ * flips the double buffer).  Line arrays P (flow at the to end), Tm (mean of
+ * the two terminal phases), V1, V2 (scaled phase duals before this
+ * iteration's update) are [T][L][Kpp]; Td ([T][Kpp]) is the half phase
+ * difference of each contingency's outaged line; node arrays U (scaled
+ * price), W (= pbar + U) and TB (thetabar) are [T][N][Kpp]; device arrays
+ * pnc, thnc, vbar (contingency mean of the phase duals) are [G+D+B][T].
+ * Contingency k < K+1 is innermost, padded to Kpp.  Element types:
+ * state_dtype for all but V1, V2 (dual_dtype).  Synchronises. */
+typedef struct {
+  int32_t N, T, K, Kpp, L, Jnc;
+  int32_t state_dtype, dual_dtype;
+  size_t P, Tm, V1, V2, Td, U, W, TB, pnc, thnc, vbar;
+} opf_layout;
+opf_status opf_state_layout(opf_ctx* ctx, int32_t instance, opf_layout* out);
+
+/* Bytes of an exported iterate (single instance, FP32 or FP64 duals). */
+opf_status opf_state_size(opf_ctx* ctx, size_t* bytes);
+
+/* Copies the whole iterate (line, node and device state, inner ADMM state of
+ * ramp generators and batteries) and the current penalties into dst (host
+ * or device memory, >= opf_state_size bytes).  Synchronises. */
+opf_status opf_get_state(opf_ctx* ctx, void* dst, size_t bytes);
+
+/* Warm start: replaces the iterate with one exported by opf_get_state from a
+ * network of the same shape (the data, e.g. loads or capacities, may
+ * differ), continues with its penalties, and restarts the iteration count
+ * at 0.  The exported precision must be one this context holds.  Rejects
+ * foreign or mismatched blobs with OPF_E_INVALID before changing anything.
+ * Synchronises. */
+opf_status opf_set_state(opf_ctx* ctx, const void* src, size_t bytes);
+
+/* ---- Derivatives through unrolled iterations (Section 4.4, sensitivities
+ * of Section 5.5) ------------------------------------------------------------
+ * The iteration map is piecewise linear in the iterate and in the data, so
+ * the derivative of the iterate after n iterations with respect to the load
+ * demand, the line capacities and the generator upper limits is a product of
+ * per-iteration Jacobians.  The library computes its transpose-vector product
+ * (reverse mode) with hand-written kernels: the forward run stores the
+ * penalty schedule (held fixed, as a constant of the map) and checkpoints
+ * of the iterate every checkpoint_every iterations; the reverse pass
+ * recomputes each segment from its checkpoint, keeping every iterate of the
+ * segment, and walks it backwards.  At a clip whose argument equals a bound
+ * the derivative passes the argument through.  One instance, FP64 or FP32
+ * iterate with FP32 or FP64 duals (not BF16), inner_iters <= 32. */
+
+/* Bytes of device memory the tape of an n_iters run needs, for the loaded
+ * network and the active precision: (ceil(n/C) + 1 + C) iterate snapshots,
+ * the penalty history and the adjoint arrays. */
+opf_status opf_tape_workspace_size(opf_ctx* ctx, int32_t n_iters, int32_t checkpoint_every,
+                                   size_t* bytes);
+
+/* Resets the iterate to the zero start and runs exactly n_iters iterations
+ * (no stop on convergence or max_iter; the adaptive penalty runs as
+ * configured), recording the tape in d_tape (caller-owned device memory,
+ * 256-byte aligned, >= opf_tape_workspace_size bytes, borrowed until the next
+ * opf_tape_forward, opf_load_network or opf_destroy).  Afterwards the iterate,
+ * residuals and fields are those after n_iters iterations.  Synchronises. */
+opf_status opf_tape_forward(opf_ctx* ctx, int32_t n_iters, int32_t checkpoint_every,
+                            void* d_tape, size_t bytes);
+
+/* Reverse pass over the recorded run.  Cotangent: d_cot_power (device,
+ * [G+D+B][T] doubles, generator/load/battery order, or NULL for zero) on the
+ * final device powers, plus cot_objective times the objective of the final
+ * iterate (generator cost + battery alpha * discharge).  Writes (device,
+ * doubles; any may be NULL): d_grad_load [D][T], derivative with respect to
+ * the load demand d; d_grad_cap [L], with respect to the line capacities;
+ * d_grad_pmax [G][T], with respect to the generator upper limits.  The
+ * iterate is left as opf_tape_forward left it.  Synchronises. */
+opf_status opf_adjoint(opf_ctx* ctx, const double* d_cot_power, double cot_objective,
+                       double* d_grad_load, double* d_grad_cap, double* d_grad_pmax);
+
 /* Text of the last failure on ctx (or of opf_create when ctx is NULL). */
 const char* opf_last_error(opf_ctx* ctx);
 

@@ -79,7 +79,7 @@ def _t(x, dtype=DT):
 class Network:
     """Problem data as CPU tensors, in terminal order (see module doc)."""
 
-    def __init__(self, inst, load_d=None, line_cap=None):
+    def __init__(self, inst, load_d=None, line_cap=None, gen_pmax=None):
         self.N, self.T, self.K = int(inst.N), int(inst.T), int(inst.K)
         self.Kp = self.K + 1
         self.L = int(len(inst.line_from))
@@ -108,7 +108,8 @@ class Network:
                 alive[k, o] = 0.0
         self.alive = alive
         self.gen_c2, self.gen_c1 = _t(inst.gen_c2), _t(inst.gen_c1)
-        self.gen_pmin, self.gen_pmax = _t(inst.gen_pmin), _t(inst.gen_pmax)
+        self.gen_pmin = _t(inst.gen_pmin)
+        self.gen_pmax = _t(inst.gen_pmax) if gen_pmax is None else gen_pmax
         ramp = _t(inst.gen_ramp)
         self.gen_ramp = ramp
         self.is_ramp = (ramp > 0) & torch.isfinite(ramp) & torch.tensor(self.T > 1)
@@ -319,8 +320,9 @@ class Residual:
 class Solver:
     """Runs the message-passing iteration from the all-zero start."""
 
-    def __init__(self, inst, opt: Optional[Options] = None, load_d=None, line_cap=None):
-        self.net = net = Network(inst, load_d=load_d, line_cap=line_cap)
+    def __init__(self, inst, opt: Optional[Options] = None, load_d=None, line_cap=None,
+                 gen_pmax=None):
+        self.net = net = Network(inst, load_d=load_d, line_cap=line_cap, gen_pmax=gen_pmax)
         self.opt = opt or Options()
         self.rho_p = float(self.opt.rho_p)
         self.rho_th = float(self.opt.rho_theta)

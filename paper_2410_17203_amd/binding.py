@@ -81,6 +81,14 @@ class Tuning(Structure):
                 ("ms_per_iter", c_double), ("from_cache", c_int32)]
 
 
+class Layout(Structure):
+    _fields_ = [("N", c_int32), ("T", c_int32), ("K", c_int32), ("Kpp", c_int32),
+                ("L", c_int32), ("Jnc", c_int32), ("state_dtype", c_int32),
+                ("dual_dtype", c_int32),
+                *[(n, c_size_t) for n in ["P", "Tm", "V1", "V2", "Td", "U", "W", "TB", "pnc",
+                                          "thnc", "vbar"]]]
+
+
 class OpfError(RuntimeError):
     pass
 
@@ -120,6 +128,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "opf_field_size_i": (c_int32, [P, c_int32, c_int32, POINTER(c_size_t)]),
         "opf_get_field_i": (c_int32, [P, c_int32, c_int32, c_void_p, c_size_t]),
         "opf_autotune": (c_int32, [P, c_int32, c_char_p, POINTER(Tuning)]),
+        "opf_state_layout": (c_int32, [P, c_int32, POINTER(Layout)]),
+        "opf_state_size": (c_int32, [P, POINTER(c_size_t)]),
+        "opf_get_state": (c_int32, [P, c_void_p, c_size_t]),
+        "opf_set_state": (c_int32, [P, c_void_p, c_size_t]),
+        "opf_tape_workspace_size": (c_int32, [P, c_int32, c_int32, POINTER(c_size_t)]),
+        "opf_tape_forward": (c_int32, [P, c_int32, c_int32, c_void_p, c_size_t]),
+        "opf_adjoint": (c_int32, [P, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
         "opf_last_error": (c_char_p, [P]),
         "opf_destroy": (None, [P]),
     }
@@ -282,6 +297,83 @@ class Solver:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    # -- the iterate: zero-copy views, export, warm start ----------------------
+    def layout(self, instance: int = 0) -> Dict:
+        lay = Layout()
+        self._check(self.lib.opf_state_layout(self.ctx, int(instance), byref(lay)))
+        return {name: getattr(lay, name) for name, _ in lay._fields_}
+
+    def view(self, name: str, instance: int = 0):
+        """Zero-copy view of one array of the current iterate in the library's
+        own layout ([T][L][Kpp], [T][N][Kpp] or [Jnc][T]); valid until the
+        next iteration."""
+        torch = self.torch
+        lay = self.layout(instance)
+        dt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+        is_dual = name in ("V1", "V2")
+        dtype = dt[lay["dual_dtype"] if is_dual else lay["state_dtype"]]
+        T, L, N, Kpp, J = lay["T"], lay["L"], lay["N"], lay["Kpp"], lay["Jnc"]
+        shape = {"P": (T, L, Kpp), "Tm": (T, L, Kpp), "V1": (T, L, Kpp), "V2": (T, L, Kpp),
+                 "Td": (T, Kpp), "U": (T, N, Kpp), "W": (T, N, Kpp), "TB": (T, N, Kpp),
+                 "pnc": (J, T), "thnc": (J, T), "vbar": (J, T)}[name]
+        esize = torch.empty((), dtype=dtype).element_size()
+        n = int(np.prod(shape))
+        off = lay[name]
+        return self.ws[off:off + n * esize].view(dtype).view(shape)
+
+    def get_state(self):
+        """The whole iterate and penalties as a uint8 device tensor."""
+        torch = self.torch
+        nbytes = c_size_t()
+        self._check(self.lib.opf_state_size(self.ctx, byref(nbytes)))
+        out = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.opf_get_state(self.ctx, c_void_p(out.data_ptr()), nbytes))
+        return out
+
+    def set_state(self, blob):
+        """Warm start from a blob returned by get_state (same network shape)."""
+        blob = blob.contiguous()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._check(self.lib.opf_set_state(self.ctx, c_void_p(blob.data_ptr()),
+                                           c_size_t(blob.numel())))
+
+    # -- derivatives through unrolled iterations ------------------------------
+    def tape_forward(self, n_iters: int, checkpoint_every: int = 50) -> Dict:
+        """Runs exactly n_iters iterations from the zero start, recording what
+        the adjoint needs; returns the residual record of the last one."""
+        torch = self.torch
+        nbytes = c_size_t()
+        self._check(self.lib.opf_tape_workspace_size(self.ctx, int(n_iters),
+                                                     int(checkpoint_every), byref(nbytes)))
+        self.tape = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        self._check(self.lib.opf_tape_forward(self.ctx, int(n_iters), int(checkpoint_every),
+                                              c_void_p(self.tape.data_ptr()), nbytes))
+        return self.residuals()
+
+    def adjoint(self, cot_power=None, cot_objective: float = 0.0) -> Dict:
+        """Reverse pass of the recorded run.  cot_power: [G+D+B, T] weights on
+        the final device powers (or None); cot_objective: weight of the final
+        objective.  Returns float64 device tensors: 'load' [D, T], 'cap' [L],
+        'pmax' [G, T] (derivatives w.r.t. demand, line capacity, generator
+        upper limit)."""
+        torch = self.torch
+        inst = self.insts[0]
+        G, D, T, L = len(inst.gen_node), len(inst.load_node), int(inst.T), len(inst.line_from)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        cot = None
+        if cot_power is not None:
+            cot = torch.as_tensor(cot_power, **f64).reshape(self.Jnc, T).contiguous()
+        out = {"load": torch.zeros(D, T, **f64), "cap": torch.zeros(L, **f64),
+               "pmax": torch.zeros(G, T, **f64)}
+        torch.cuda.current_stream(self.device).synchronize()
+
+        def ptr(x):
+            return c_void_p(x.data_ptr()) if x is not None and x.numel() > 0 else None
+        self._check(self.lib.opf_adjoint(self.ctx, ptr(cot), float(cot_objective),
+                                         ptr(out["load"]), ptr(out["cap"]), ptr(out["pmax"])))
+        return out
 
     def autotune(self, trials: int = 5, cache_path: Optional[str] = None) -> Dict:
         t = Tuning()

@@ -1,0 +1,587 @@
+// Reverse mode of unrolled message-passing iterations (arXiv 2410.17203,
+// Section 4.4; the sensitivities of Section 5.5): derivatives of the final
+// device powers and of the cost with respect to problem data, through the
+// iterations, written by hand instead of recorded by a tracing framework.  The forward pass records the
+// penalty schedule and snapshots of the iterate; the reverse pass walks the
+// iterations backwards, recomputing from each snapshot which clips were
+// active and applying the transposed piecewise-linear maps:
+//
+//   k_adj_nodeavg  adjoint of the contingency means of W and thetabar that
+//                  the next iteration's device step read (CSR sum per node);
+//   k_adj_sweep    reverse of the node update, the node averages and the line
+//                  prox (the from node of each line stores its adjoint, both
+//                  end nodes accumulate their own side, fixed order, no
+//                  atomics), and the capacity derivative;
+//   k_adj_devices  reverse of the device step: the phase-dual update, the
+//                  generator clip (the generator-limit derivative), the loads
+//                  (the load derivative), and the
+//                  inner ADMM of ramp generators and batteries replayed with
+//                  recorded clip masks, then reversed through its inner
+//                  iterations (each tridiagonal solve is symmetric, so its
+//                  transpose is the same solve).
+//
+// Notation of the forward (per contingency k, period t, line l with from node
+// f and to node h): half = P / (2s) (outaged line: Td), theta1 = Tm + half,
+// theta2 = Tm - half, v1 = sv (V1 + theta1 - TB_f), z1 = -P - W_f,
+// z2 = P - W_h, xi1 = TB_f - v1, u = ca (z2 - z1) + cb (xi1 - xi2),
+// P' = clip(u, -cap, cap), Tm' = (xi1 + xi2) / 2; node: pbar = sum / deg,
+// U' = U + pbar, W' = U' + pbar, then W'' = W' + (su - 1) U', U'' = su U'.
+#include <algorithm>
+
+#include "opf_device.h"
+
+namespace opf {
+
+// Adjoint targets of one node row (16 bytes of contingencies): from the
+// adjoint of (U'', W'', TB') and of the contingency means read by the next
+// device step, the adjoints of the node's power and phase sums (divided by
+// its degree) and of the incoming price U.
+template <typename R, int VEC>
+struct NodeAdj {
+  R sp[VEC], sb[VEC], u_in[VEC];
+};
+
+template <typename R, int VEC>
+__device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, int t, int k0,
+                                NodeAdj<R, VEC>& o) {
+  using VR = Vec<R, VEC>;
+  const Topo& tp = a.tp;
+  const VR Ub = *reinterpret_cast<const VR*>(a.out.U + off);
+  const VR Wb = *reinterpret_cast<const VR*>(a.out.W + off);
+  const VR Tb = *reinterpret_cast<const VR*>(a.out.TB + off);
+  const R iKp = R(1) / R(tp.Kp);
+  const R aw = a.avw[size_t(n) * tp.T + t] * iKp;
+  const R at = a.avt[size_t(n) * tp.T + t] * iKp;
+  const R su = R(a.s.su_next);
+  const R idg = R(1) / R(tp.deg[n]);
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const bool valid = k0 + e < tp.Kp;
+    const R w2 = Wb.x[e] + aw;                       // adjoint of W''
+    const R u1 = su * Ub.x[e] + (su - R(1)) * w2;    // adjoint of U'
+    const R pb = u1 + R(2) * w2;                     // adjoint of pbar
+    o.sp[e] = valid ? pb * idg : R(0);
+    o.sb[e] = valid ? (Tb.x[e] + at) * idg : R(0);
+    o.u_in[e] = valid ? u1 + w2 : R(0);
+  }
+}
+
+// Reverse of one (period, node) row and one 16-byte vector of contingencies.
+template <typename R>
+__device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int q1, R& gsp,
+                               R& gsb) {
+  constexpr int VEC = 16 / sizeof(R);
+  using VR = Vec<R, VEC>;
+  using VI = Vec<int32_t, VEC>;
+  const Topo& tp = a.tp;
+  const int t = row / tp.N, n = row - t * tp.N;
+  const int k0 = v * VEC;
+  const size_t off = size_t(row) * tp.Kpp + k0;
+  const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+  const VR Wo = *reinterpret_cast<const VR*>(a.A.W + off);
+  const VR Bo = *reinterpret_cast<const VR*>(a.A.TB + off);
+  const R* td_old = a.A.Td + size_t(t) * tp.Kpp + k0;
+  const R* tdb_out = a.out.Td + size_t(t) * tp.Kpp + k0;
+  R* tdb_in = a.in.Td + size_t(t) * tp.Kpp + k0;
+  const R rp = R(a.s.rp), rt = R(a.s.rt), sv = R(a.s.sv);
+  NodeAdj<R, VEC> me;
+  node_adj<R, VEC>(a, off, n, t, k0, me);
+  R accW[VEC], accB[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) accW[e] = accB[e] = R(0);
+  const size_t lrow = size_t(t) * tp.L, nrow = size_t(t) * tp.N;
+  for (int q = q0; q < q1; ++q) {
+    const int2 term = tp.node_lterm[q];
+    const int l = term.x >> 1, m = term.y;
+    const bool to_end = term.x & 1;  // this node is the line's terminal-2 node
+    const size_t ol = (lrow + l) * tp.Kpp + k0;
+    const size_t oo = (nrow + m) * tp.Kpp + k0;
+    const VR P = *reinterpret_cast<const VR*>(a.A.P + ol);
+    const VR Tm = *reinterpret_cast<const VR*>(a.A.Tm + ol);
+    const VR V1 = *reinterpret_cast<const VR*>(a.A.V1 + ol);
+    const VR V2 = *reinterpret_cast<const VR*>(a.A.V2 + ol);
+    const VR Wx = *reinterpret_cast<const VR*>(a.A.W + oo);
+    const VR Bx = *reinterpret_cast<const VR*>(a.A.TB + oo);
+    const R s = R(tp.sus[l]), cap = R(tp.cap[l]);
+    LineOut<R, VEC> o;
+    line_prox<R, R, VEC>(P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx, to_end ? Bx : Bo,
+                         to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, s, cap, rp, rt, sv, o);
+    NodeAdj<R, VEC> far;
+    node_adj<R, VEC>(a, oo, m, t, k0, far);
+    const VR Pb = *reinterpret_cast<const VR*>(a.out.P + ol);
+    const VR Tmb = *reinterpret_cast<const VR*>(a.out.Tm + ol);
+    const VR V1b = *reinterpret_cast<const VR*>(a.out.V1 + ol);
+    const VR V2b = *reinterpret_cast<const VR*>(a.out.V2 + ol);
+    const R inv2s = R(0.5) / s;
+    const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;
+    const R ca = rp / den, cb = rt * inv2s / den;
+    VR Pi, Ti, V1i, V2i;
+    double* gc = a.gcap + ol;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const bool valid = k0 + e < tp.Kp;
+      const bool outg = ok.x[e] == l;
+      const R spf = to_end ? far.sp[e] : me.sp[e], sph = to_end ? me.sp[e] : far.sp[e];
+      const R sbf = to_end ? far.sb[e] : me.sb[e], sbh = to_end ? me.sb[e] : far.sb[e];
+      // adjoints of the line's outputs, including what the node sums took
+      R pt = Pb.x[e] + sph - spf;
+      const R tt = Tmb.x[e] + sbf + sbh;
+      R hb = sbf - sbh;
+      R x1, x2, z1b, z2b;
+      if (outg) {
+        hb += tdb_out[e];
+        x1 = R(0.5) * (hb + tt);
+        x2 = R(0.5) * (tt - hb);
+        z1b = z2b = R(0);
+      } else {
+        pt += hb * inv2s;
+        const bool pass = clip_pass(o.u[e], -cap, cap);
+        const R ub = pass ? pt : R(0);
+        if (!to_end && valid && !pass) gc[e] += double(o.u[e] > cap ? pt : -pt);
+        z2b = ca * ub;
+        z1b = -z2b;
+        x1 = cb * ub + R(0.5) * tt;
+        x2 = R(0.5) * tt - cb * ub;
+      }
+      const R v1b = V1b.x[e] - x1, v2b = V2b.x[e] - x2;
+      const R th1b = sv * v1b, th2b = sv * v2b;
+      const R hin = th1b - th2b;
+      R pin = z2b - z1b;
+      if (!outg) pin += hin * inv2s;
+      Pi.x[e] = valid ? pin : R(0);
+      Ti.x[e] = valid ? th1b + th2b : R(0);
+      V1i.x[e] = valid ? sv * v1b : R(0);
+      V2i.x[e] = valid ? sv * v2b : R(0);
+      if (valid) {
+        accW[e] += to_end ? -z2b : -z1b;
+        accB[e] += to_end ? x2 - th2b : x1 - th1b;
+      }
+      if (!to_end && outg && valid) tdb_in[e] = hin;
+    }
+    if (!to_end) {  // the from node stores the line's adjoint
+      *reinterpret_cast<VR*>(a.in.P + ol) = Pi;
+      *reinterpret_cast<VR*>(a.in.Tm + ol) = Ti;
+      *reinterpret_cast<VR*>(a.in.V1 + ol) = V1i;
+      *reinterpret_cast<VR*>(a.in.V2 + ol) = V2i;
+    }
+  }
+  VR Ui, Wi, Bi;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    Ui.x[e] = me.u_in[e];
+    Wi.x[e] = accW[e];
+    Bi.x[e] = accB[e];
+    gsp += me.sp[e];
+    gsb += me.sb[e];
+  }
+  *reinterpret_cast<VR*>(a.in.U + off) = Ui;
+  *reinterpret_cast<VR*>(a.in.W + off) = Wi;
+  *reinterpret_cast<VR*>(a.in.TB + off) = Bi;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
+  const int lpr = a.lanes_per_row, nv = a.nv;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int rw = lane / lpr, q = lane - rw * lpr;
+  const int rows_per_wave = kWave / lpr;
+  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  for (int64_t gi = blockIdx.x; gi < a.n_grps; gi += gridDim.x) {
+    const int64_t row = (gi * (kBlock / kWave) + w) * rows_per_wave + rw;
+    const bool act = row < NT;
+    R gsp = R(0), gsb = R(0);
+    int n = 0, t = 0;
+    if (act) {
+      t = int(row / a.tp.N);
+      n = int(row - int64_t(t) * a.tp.N);
+      const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
+      for (int v = q; v < nv; v += lpr) adj_vec<R>(a, int(row), v, q0, q1, gsp, gsb);
+    }
+    for (int d = lpr >> 1; d > 0; d >>= 1) {
+      gsp += __shfl_xor(gsp, d);
+      gsb += __shfl_xor(gsb, d);
+    }
+    if (act && q == 0) {
+      a.gsp[size_t(n) * a.tp.T + t] = gsp;
+      a.gsb[size_t(n) * a.tp.T + t] = gsb;
+    }
+  }
+}
+
+// Adjoint of the node means read by a device step: avgW enters each device's
+// prox target with sign -1, avgTB its phase and phase-dual update.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_adj_nodeavg(AdjArgs<R> a) {
+  const Topo& tp = a.tp;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= int64_t(tp.N) * tp.T) return;
+  const int n = int(i / tp.T), t = int(i - int64_t(n) * tp.T);
+  R sw = R(0), st = R(0);
+  for (int q = tp.node_nptr[n]; q < tp.node_nptr[n + 1]; ++q) {
+    const int j = tp.node_nterm[q];
+    sw -= a.dev_x[size_t(j) * tp.T + t];
+    st += a.dev_t[size_t(j) * tp.T + t];
+  }
+  a.avw[i] = sw;
+  a.avt[i] = st;
+}
+
+// Reverse of the ramp generator's inner ADMM: replays the forward with clip
+// masks, then walks the inner iterations backwards.  pb: adjoint of the
+// output power; adj: adjoint of the inner state after the call (read) and
+// before it (written back, lambdas times su).  Returns the adjoint of the
+// prox target X.
+template <typename R, int E>
+__device__ void ramp_adj(const Topo& tp, const R* st, R* adj, int r, int g, const R (&X)[E],
+                         R rho_hat, R omega, R su, int n_inner, int lane, const R (&pb)[E],
+                         R (&Xb)[E], double* gpmax) {
+  const int T = tp.T;
+  const size_t nRT = size_t(tp.nR) * T;
+  const size_t o = size_t(r) * T;
+  ClipMasks<E, 2> mk;
+  R pfwd[E];
+  ramp_prox<R, E>(tp, st, nullptr, r, g, X, rho_hat, omega, su, n_inner, lane, pfwd, mk);
+  const R c2 = R(tp.gen_c2[g]);
+  const R w = R(2) * c2 + rho_hat;
+  const R eo = -omega;
+  R mul[E], invm[E];
+  thomas_factors<R, E>(T, eo, [&](int t) { return w + omega + omega * R((t > 0) + (t < T - 1)); },
+                       lane, mul, invm);
+  R Bb[E], Lb[E], Br[E], Lr[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    Bb[e] = t < T ? adj[0 * nRT + o + t] : R(0);
+    Lb[e] = t < T ? adj[1 * nRT + o + t] : R(0);
+    Br[e] = t < T - 1 ? adj[2 * nRT + o + t] : R(0);
+    Lr[e] = t < T - 1 ? adj[3 * nRT + o + t] : R(0);
+    Xb[e] = R(0);
+  }
+  for (int it = n_inner - 1; it >= 0; --it) {
+    R xb[E], dpb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      xb[e] = (it == n_inner - 1 && t < T) ? pb[e] : R(0);
+      dpb[e] = R(0);
+      if (t < T) {
+        const R bn = Bb[e] - Lb[e];
+        const R thru = mk.pass(0, it, e) ? bn : R(0);
+        if (mk.at_high(0, it, e)) gpmax[size_t(g) * T + t] += double(bn);
+        xb[e] += Lb[e] + thru;
+        Lb[e] += thru;
+      }
+      if (t < T - 1) {
+        const R rn = Br[e] - Lr[e];
+        const R thru = mk.pass(1, it, e) ? rn : R(0);
+        dpb[e] = Lr[e] + thru;
+        Lr[e] += thru;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const R prev = prev_slot<R, E>(dpb, e);  // dp_{t-1} = x_t - x_{t-1}
+      xb[e] += prev - dpb[e];
+    }
+    thomas_solve<R, E>(T, eo, mul, invm, xb, lane);  // symmetric: transpose solve
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R nx = next_slot<R, E>(xb, e);
+      if (t < T) {
+        Xb[e] += rho_hat * xb[e];
+        Bb[e] = omega * xb[e];
+        Lb[e] -= omega * xb[e];
+      }
+      if (t < T - 1) {
+        const R qb = omega * (nx - xb[e]);
+        Br[e] = qb;
+        Lr[e] -= qb;
+      } else {
+        Br[e] = Lr[e] = R(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    if (t < T) {
+      adj[0 * nRT + o + t] = Bb[e];
+      adj[1 * nRT + o + t] = su * Lb[e];
+      adj[2 * nRT + o + t] = Br[e];
+      adj[3 * nRT + o + t] = su * Lr[e];
+    }
+  }
+}
+
+// Reverse of the battery's inner ADMM; db: adjoint of the discharge delta of
+// the last x-update (the objective's alpha * sum delta), besides pb.
+template <typename R, int E>
+__device__ void battery_adj(const Topo& tp, const R* st, R* adj, int b, const R (&X)[E],
+                            R rho_hat, R omega, R su, int n_inner, int lane, const R (&pb)[E],
+                            R db, R (&Xb)[E]) {
+  const int T = tp.T;
+  const size_t nBT = size_t(tp.B) * T;
+  const size_t o = size_t(b) * T;
+  ClipMasks<E, 3> mk;
+  R pfwd[E];
+  double obj = 0.0;
+  battery_prox<R, E>(tp, st, nullptr, b, X, rho_hat, omega, su, n_inner, lane, pfwd, obj, mk);
+  const BatK<R> k(tp, b, rho_hat, omega);
+  const R eo = -k.iw;
+  R mul[E], invm[E];
+  thomas_factors<R, E>(T, eo, [&](int t) { return k.kappa + k.iw * R((t < T - 1) + (t > 0)); },
+                       lane, mul, invm);
+  R Bc[E], Lc[E], Bd[E], Ld[E], Bs[E], Ls[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    const bool ok = t < T, oks = t >= 1 && t < T;
+    Bc[e] = ok ? adj[0 * nBT + o + t] : R(0);
+    Lc[e] = ok ? adj[1 * nBT + o + t] : R(0);
+    Bd[e] = ok ? adj[2 * nBT + o + t] : R(0);
+    Ld[e] = ok ? adj[3 * nBT + o + t] : R(0);
+    Bs[e] = oks ? adj[4 * nBT + o + t] : R(0);
+    Ls[e] = oks ? adj[5 * nBT + o + t] : R(0);
+    Xb[e] = R(0);
+  }
+  for (int it = n_inner - 1; it >= 0; --it) {
+    R cb[E], dlb[E], sb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const bool lastit = it == n_inner - 1;
+      cb[e] = dlb[e] = sb[e] = R(0);
+      if (t < T) {
+        cb[e] = lastit ? -pb[e] : R(0);
+        dlb[e] = lastit ? pb[e] + db : R(0);
+        R bn = Bc[e] - Lc[e];
+        R thru = mk.pass(0, it, e) ? bn : R(0);
+        cb[e] += Lc[e] + thru;
+        Lc[e] += thru;
+        bn = Bd[e] - Ld[e];
+        thru = mk.pass(1, it, e) ? bn : R(0);
+        dlb[e] += Ld[e] + thru;
+        Ld[e] += thru;
+      }
+      if (t >= 1 && t < T) {
+        const R bn = Bs[e] - Ls[e];
+        const R thru = mk.pass(2, it, e) ? bn : R(0);
+        sb[e] = Ls[e] + thru;
+        Ls[e] += thru;
+      }
+    }
+    // nu_t enters c_t, delta_t, s_t (+1/omega) and s_{t+1} (-1/omega)
+    R nub[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R sn = next_slot<R, E>(sb, e);
+      nub[e] = t < T ? k.hgc * cb[e] + k.hgd * dlb[e] + (sb[e] - sn) * k.iw : R(0);
+    }
+    thomas_solve<R, E>(T, eo, mul, invm, nub, lane);  // symmetric: transpose solve
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      const R rprev = prev_slot<R, E>(nub, e);  // rhs_{t-1} holds + qs_t
+      if (t < T) {
+        const R qsb = sb[e] + (t >= 1 ? rprev : R(0)) - nub[e];
+        const R hrcb = cb[e] - k.eta * nub[e];
+        const R hrdb = dlb[e] + nub[e];
+        const R rcb = k.h11 * hrcb + k.h12 * hrdb;
+        const R rdb = k.h12 * hrcb + k.h11 * hrdb;
+        Bc[e] = omega * rcb;
+        Lc[e] -= omega * rcb;
+        Bd[e] = omega * rdb;
+        Ld[e] -= omega * rdb;
+        Xb[e] += rho_hat * (rdb - rcb);
+        if (t >= 1) {
+          Bs[e] = qsb;
+          Ls[e] -= qsb;
+        } else {
+          Bs[e] = Ls[e] = R(0);
+        }
+      } else {
+        Bc[e] = Lc[e] = Bd[e] = Ld[e] = Bs[e] = Ls[e] = R(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    if (t < T) {
+      adj[0 * nBT + o + t] = Bc[e];
+      adj[1 * nBT + o + t] = su * Lc[e];
+      adj[2 * nBT + o + t] = Bd[e];
+      adj[3 * nBT + o + t] = su * Ld[e];
+      if (t >= 1) {
+        adj[4 * nBT + o + t] = Bs[e];
+        adj[5 * nBT + o + t] = su * Ls[e];
+      }
+    }
+  }
+}
+
+// Reverse of the device step, one device per wavefront (T across lanes).
+template <typename R, int E>
+__global__ void __launch_bounds__(kBlock) k_adj_devices(AdjArgs<R> a) {
+  const Topo& tp = a.tp;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (kBlock / kWave) + w;
+  if (j >= tp.Jnc) return;
+  const int T = tp.T;
+  const int n = tp.nc_node[j];
+  const R sv = R(a.s.sv), su = R(a.s.su);
+  const R rho_hat = R(tp.Kp) * R(a.s.rp);
+  const R omega = R(a.omega_scale) * rho_hat;
+  R X[E], pb[E], Xb[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    X[e] = pb[e] = Xb[e] = R(0);
+    if (t < T) {
+      const size_t o = size_t(j) * T + t, on = size_t(n) * T + t;
+      pb[e] = a.dev_p[o] + a.gsp[on];
+      const R thb = a.dev_th[o] + a.gsb[on];
+      const R vtot = a.dev_v[o] - thb;  // adjoint of the updated phase dual
+      a.dev_t[o] = thb - sv * vtot;
+      a.dev_v[o] = sv * vtot;
+      a.dev_th[o] = sv * vtot;
+      X[e] = a.pnc[o] - a.avgW[on];
+    }
+  }
+  if (j < tp.G) {
+    const int r = tp.ramp_idx[j];
+    if (r < 0) {
+      const R c2 = R(tp.gen_c2[j]), c1 = R(tp.gen_c1[j]);
+      const R slope = rho_hat / (R(2) * c2 + rho_hat);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int t = lane * E + e;
+        if (t < T) {
+          const R y = gen_target(X[e], c1, c2, rho_hat);
+          const bool pass = clip_pass(y, R(tp.gen_pmin[size_t(j) * T + t]),
+                                      R(tp.gen_pmax[size_t(j) * T + t]));
+          Xb[e] = pass ? slope * pb[e] : R(0);
+          if (y > R(tp.gen_pmax[size_t(j) * T + t])) a.gpmax[size_t(j) * T + t] += double(pb[e]);
+        }
+      }
+    } else {
+      ramp_adj<R, E>(tp, a.ramp_st, a.ramp_adj, r, j, X, rho_hat, omega, su, a.inner_iters, lane,
+                     pb, Xb, a.gpmax);
+    }
+  } else if (j < tp.G + tp.D) {
+    const int d = j - tp.G;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int t = lane * E + e;
+      if (t < T) a.gload[size_t(d) * T + t] -= double(pb[e]);  // p = -d
+    }
+  } else {
+    const int b = j - tp.G - tp.D;
+    const R db = a.s.last ? R(a.w_obj * tp.bat_alpha[b]) : R(0);
+    battery_adj<R, E>(tp, a.bat_st, a.bat_adj, b, X, rho_hat, omega, su, a.inner_iters, lane, pb,
+                      db, Xb);
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = lane * E + e;
+    if (t < T) {
+      const size_t o = size_t(j) * T + t;
+      a.dev_p[o] = Xb[e];  // the prox target is p - avgW
+      a.dev_x[o] = Xb[e];
+    }
+  }
+}
+
+// Cotangent of the final iterate: the caller's weights on the device powers
+// plus w_obj times the derivative of the generator cost.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_adj_init(AdjArgs<R> a, const double* cot) {
+  const Topo& tp = a.tp;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= int64_t(tp.Jnc) * tp.T) return;
+  const int j = int(i / tp.T);
+  double v = cot ? cot[i] : 0.0;
+  if (j < tp.G) v += a.w_obj * (2.0 * tp.gen_c2[j] * double(a.pnc[i]) + tp.gen_c1[j]);
+  a.dev_p[i] = R(v);
+}
+
+// Capacity derivative: sum over periods and contingencies.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_adj_cap(AdjArgs<R> a, double* grad) {
+  const Topo& tp = a.tp;
+  const int l = blockIdx.x;
+  __shared__ double sh[kBlock / kWave];
+  double s = 0.0;
+  const int64_t per = int64_t(tp.T) * tp.Kpp;
+  for (int64_t i = threadIdx.x; i < per; i += kBlock) {
+    const int t = int(i / tp.Kpp), k = int(i - int64_t(t) * tp.Kpp);
+    s += a.gcap[(size_t(t) * tp.L + l) * tp.Kpp + k];
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) grad[l] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(CopyList cl) {
+  const int i = blockIdx.y;
+  const char* src = cl.src[i];
+  char* dst = cl.dst[i];
+  const size_t nb = cl.bytes[i];
+  const size_t n16 = nb / 16;
+  const size_t stride = size_t(gridDim.x) * kBlock;
+  for (size_t q = size_t(blockIdx.x) * kBlock + threadIdx.x; q < n16; q += stride)
+    reinterpret_cast<uint4*>(dst)[q] = reinterpret_cast<const uint4*>(src)[q];
+  for (size_t q = n16 * 16 + size_t(blockIdx.x) * kBlock + threadIdx.x; q < nb; q += stride)
+    dst[q] = src[q];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+template <typename R>
+void launch_adj_iteration(const AdjArgs<R>& a, hipStream_t s) {
+  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
+  k_adj_nodeavg<R><<<int((NT + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
+  const int64_t grid = std::min<int64_t>(a.n_grps, 8192);
+  k_adj_sweep<R><<<int(grid), kBlock, 0, s>>>(a);
+  const int nblk = (a.tp.Jnc + 3) / 4;
+  if (nblk == 0) return;
+  const int E = (a.tp.T + kWave - 1) / kWave;
+  switch (E) {
+    case 1: k_adj_devices<R, 1><<<nblk, kBlock, 0, s>>>(a); break;
+    case 2: k_adj_devices<R, 2><<<nblk, kBlock, 0, s>>>(a); break;
+    case 3: k_adj_devices<R, 3><<<nblk, kBlock, 0, s>>>(a); break;
+    default: k_adj_devices<R, 4><<<nblk, kBlock, 0, s>>>(a); break;
+  }
+}
+
+template <typename R>
+void launch_adj_init(const AdjArgs<R>& a, const double* cot, hipStream_t s) {
+  const int64_t n = int64_t(a.tp.Jnc) * a.tp.T;
+  if (n == 0) return;
+  k_adj_init<R><<<int((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(a, cot);
+}
+
+template <typename R>
+void launch_adj_cap(const AdjArgs<R>& a, double* grad, hipStream_t s) {
+  if (a.tp.L == 0) return;
+  k_adj_cap<R><<<a.tp.L, kBlock, 0, s>>>(a, grad);
+}
+
+void launch_copy(const CopyList& cl, hipStream_t s) {
+  if (cl.n == 0) return;
+  size_t mx = 0;
+  for (int i = 0; i < cl.n; ++i) mx = std::max(mx, cl.bytes[i]);
+  const size_t blocks = std::min<size_t>(1024, (mx / 16 + kBlock - 1) / kBlock + 1);
+  k_copy<<<dim3(unsigned(blocks), unsigned(cl.n)), kBlock, 0, s>>>(cl);
+}
+
+template void launch_adj_iteration<double>(const AdjArgs<double>&, hipStream_t);
+template void launch_adj_iteration<float>(const AdjArgs<float>&, hipStream_t);
+template void launch_adj_init<double>(const AdjArgs<double>&, const double*, hipStream_t);
+template void launch_adj_init<float>(const AdjArgs<float>&, const double*, hipStream_t);
+template void launch_adj_cap<double>(const AdjArgs<double>&, double*, hipStream_t);
+template void launch_adj_cap<float>(const AdjArgs<float>&, double*, hipStream_t);
+
+}  // namespace opf

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -71,6 +72,34 @@ struct Inst {
 };
 
 // Offsets of everything one instance holds in the workspace.
+// Snapshot of the iterate of one precision: 15 arrays (line P, Tm, V1, V2,
+// outaged half difference, node U, W, thetabar, the two node means, device
+// power/phase/phase dual, ramp and battery inner states), packed.
+constexpr int kSnapArrays = 15;
+struct SnapLayout {
+  size_t off[kSnapArrays];
+  size_t bytes[kSnapArrays];
+  size_t total;
+};
+
+// Tape of a forward run: penalty-schedule history, checkpoints every C
+// iterations, the final iterate, C per-iteration snapshots of the segment
+// being reversed, and the adjoint arrays.
+struct TapePlan {
+  bool ready = false;
+  int n_iters = 0, every = 0, precision = 0;
+  char* base = nullptr;
+  size_t bytes = 0;
+  SnapLayout snap{};
+  size_t hist = 0, ckpt = 0, n_ckpt = 0, final_snap = 0, seg = 0;
+  size_t adj_line[2][4] = {}, adj_td[2] = {}, adj_node[2][3] = {};
+  size_t gsp = 0, gsb = 0, avw = 0, avt = 0;
+  size_t dev[5] = {};
+  size_t ramp_adj = 0, bat_adj = 0, gcap = 0, gload = 0, gpmax = 0;
+  size_t adj_begin = 0, adj_end = 0;
+  size_t total = 0;
+};
+
 struct InstPlan {
   size_t ctl, ring;
   size_t line_from, line_to, sus, cap, outage_k, node_lptr, node_lterm, node_nptr, node_nterm, deg,
@@ -119,6 +148,9 @@ struct opf_ctx {
   int64_t t_n[OPF_KERNEL_COUNT] = {0, 0, 0, 0};
   // graphs keyed by (precision, length)
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  // record of a forward run for the adjoint
+  TapePlan tape{};
+  std::vector<Ctl> tape_hist;
 };
 
 namespace {
@@ -831,6 +863,8 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
   if (s != OPF_OK) return s;
   s = reset_state(c);
   if (s != OPF_OK) return s;
+  c->tape = TapePlan{};
+  c->tape_hist.clear();
   c->loaded = true;
   return OPF_OK;
 }
@@ -875,6 +909,303 @@ bool all_done(const opf_ctx* c) {
   for (size_t i = 0; i < c->inst.size(); ++i)
     if (!c->h_ctl[i].done) return false;
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Tape of a forward run and its adjoint.
+
+size_t elem_size(int precision) { return precision == 0 ? sizeof(double) : sizeof(float); }
+
+SnapLayout snap_layout(const Inst& s, int precision) {
+  const size_t S = elem_size(precision);
+  const size_t line = size_t(s.L) * s.T * s.Kpp * S, node = size_t(s.N) * s.T * s.Kpp * S;
+  const size_t sizes[kSnapArrays] = {
+      line, line, line, line, size_t(s.T) * s.Kpp * S, node, node, node,
+      size_t(s.N) * s.T * S, size_t(s.N) * s.T * S, size_t(s.Jnc) * s.T * S,
+      size_t(s.Jnc) * s.T * S, size_t(s.Jnc) * s.T * S, 4 * size_t(s.nR) * s.T * S,
+      6 * size_t(s.B) * s.T * S};
+  SnapLayout sl{};
+  Layout L;
+  for (int i = 0; i < kSnapArrays; ++i) {
+    sl.bytes[i] = sizes[i];
+    sl.off[i] = L.take(sizes[i]);
+  }
+  sl.total = L.total;
+  return sl;
+}
+
+TapePlan plan_tape(const Inst& s, int precision, int M, int C) {
+  TapePlan t;
+  t.n_iters = M;
+  t.every = C;
+  t.precision = precision;
+  t.snap = snap_layout(s, precision);
+  const size_t S = elem_size(precision);
+  Layout L;
+  t.hist = L.take(sizeof(Ctl) * (size_t(M) + 1));
+  t.n_ckpt = (size_t(M) + C - 1) / C;
+  t.ckpt = L.take(t.snap.total * t.n_ckpt);
+  t.final_snap = L.take(t.snap.total);
+  t.seg = L.take(t.snap.total * size_t(C));
+  t.adj_begin = L.total;
+  const size_t line = size_t(s.L) * s.T * s.Kpp * S, node = size_t(s.N) * s.T * s.Kpp * S;
+  for (int b = 0; b < 2; ++b) {
+    for (int q = 0; q < 4; ++q) t.adj_line[b][q] = L.take(line);
+    t.adj_td[b] = L.take(size_t(s.T) * s.Kpp * S);
+    for (int q = 0; q < 3; ++q) t.adj_node[b][q] = L.take(node);
+  }
+  const size_t nt = size_t(s.N) * s.T * S, jt = size_t(s.Jnc) * s.T * S;
+  t.gsp = L.take(nt);
+  t.gsb = L.take(nt);
+  t.avw = L.take(nt);
+  t.avt = L.take(nt);
+  for (int q = 0; q < 5; ++q) t.dev[q] = L.take(jt);
+  t.ramp_adj = L.take(4 * size_t(s.nR) * s.T * S);
+  t.bat_adj = L.take(6 * size_t(s.B) * s.T * S);
+  t.gcap = L.take(size_t(s.L) * s.T * s.Kpp * sizeof(double));
+  t.gload = L.take(size_t(s.D) * s.T * sizeof(double));
+  t.gpmax = L.take(size_t(s.G) * s.T * sizeof(double));
+  t.adj_end = L.total;
+  t.total = L.total;
+  return t;
+}
+
+// Device arrays of the iterate (buffer cur) in snapshot order.
+template <typename R>
+void state_arrays(const State<R, R>& st, int cur, char* (&out)[kSnapArrays]) {
+  const Buf<R, R>& b = st.buf[cur];
+  char* a[kSnapArrays] = {
+      reinterpret_cast<char*>(b.P), reinterpret_cast<char*>(b.Tm), reinterpret_cast<char*>(b.V1),
+      reinterpret_cast<char*>(b.V2), reinterpret_cast<char*>(b.Td), reinterpret_cast<char*>(b.U),
+      reinterpret_cast<char*>(b.W), reinterpret_cast<char*>(b.TB),
+      reinterpret_cast<char*>(st.avgW), reinterpret_cast<char*>(st.avgTB),
+      reinterpret_cast<char*>(st.pnc), reinterpret_cast<char*>(st.thnc),
+      reinterpret_cast<char*>(st.vbar), reinterpret_cast<char*>(st.ramp_st),
+      reinterpret_cast<char*>(st.bat_st)};
+  for (int i = 0; i < kSnapArrays; ++i) out[i] = a[i];
+}
+
+template <typename R>
+const State<R, R>& inst_state(const Inst& s);
+template <>
+const State<double, double>& inst_state<double>(const Inst& s) {
+  return s.st64;
+}
+template <>
+const State<float, float>& inst_state<float>(const Inst& s) {
+  return s.st32;
+}
+
+// Copies the iterate (buffer cur) into the snapshot at snap, or back.
+template <typename R>
+void snapshot(opf_ctx* c, const Inst& s, int cur, char* snap, bool to_snap) {
+  char* arr[kSnapArrays];
+  state_arrays<R>(inst_state<R>(s), cur, arr);
+  CopyList cl{};
+  const SnapLayout& sl = c->tape.snap;
+  for (int i = 0; i < kSnapArrays; ++i) {
+    if (sl.bytes[i] == 0) continue;
+    cl.src[cl.n] = to_snap ? arr[i] : snap + sl.off[i];
+    cl.dst[cl.n] = to_snap ? snap + sl.off[i] : arr[i];
+    cl.bytes[cl.n] = sl.bytes[i];
+    ++cl.n;
+  }
+  launch_copy(cl, c->stream);
+}
+
+char* tape_ptr(const opf_ctx* c, size_t off) { return c->tape.base + off; }
+
+// Adjoint kernel arguments for the reverse of iteration i from the snapshot
+// at snap; ob selects which adjoint buffer holds the adjoint after it.
+template <typename R>
+AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double w_obj) {
+  const TapePlan& t = c->tape;
+  const SnapLayout& sl = t.snap;
+  AdjArgs<R> a{};
+  a.tp = s.topo;
+  auto sp = [&](int i) { return reinterpret_cast<R*>(const_cast<char*>(snap) + sl.off[i]); };
+  a.A.P = sp(0);
+  a.A.Tm = sp(1);
+  a.A.V1 = sp(2);
+  a.A.V2 = sp(3);
+  a.A.Td = sp(4);
+  a.A.U = sp(5);
+  a.A.W = sp(6);
+  a.A.TB = sp(7);
+  a.avgW = sp(8);
+  a.avgTB = sp(9);
+  a.pnc = sp(10);
+  a.thnc = sp(11);
+  a.vbar = sp(12);
+  a.ramp_st = sp(13);
+  a.bat_st = sp(14);
+  auto tp = [&](size_t off) { return reinterpret_cast<R*>(tape_ptr(c, off)); };
+  for (int side = 0; side < 2; ++side) {
+    const int b = side == 0 ? ob : ob ^ 1;
+    AdjBuf<R>& d = side == 0 ? a.out : a.in;
+    d.P = tp(t.adj_line[b][0]);
+    d.Tm = tp(t.adj_line[b][1]);
+    d.V1 = tp(t.adj_line[b][2]);
+    d.V2 = tp(t.adj_line[b][3]);
+    d.Td = tp(t.adj_td[b]);
+    d.U = tp(t.adj_node[b][0]);
+    d.W = tp(t.adj_node[b][1]);
+    d.TB = tp(t.adj_node[b][2]);
+  }
+  a.gsp = tp(t.gsp);
+  a.gsb = tp(t.gsb);
+  a.avw = tp(t.avw);
+  a.avt = tp(t.avt);
+  a.dev_p = tp(t.dev[0]);
+  a.dev_th = tp(t.dev[1]);
+  a.dev_v = tp(t.dev[2]);
+  a.dev_x = tp(t.dev[3]);
+  a.dev_t = tp(t.dev[4]);
+  a.ramp_adj = tp(t.ramp_adj);
+  a.bat_adj = tp(t.bat_adj);
+  a.gcap = reinterpret_cast<double*>(tape_ptr(c, t.gcap));
+  a.gload = reinterpret_cast<double*>(tape_ptr(c, t.gload));
+  a.gpmax = reinterpret_cast<double*>(tape_ptr(c, t.gpmax));
+  const Geom& g = t.precision == 0 ? s.geom64 : s.geom32;
+  a.nv = g.nv;
+  a.lanes_per_row = g.lanes_per_row;
+  a.n_grps = g.n_grps;
+  a.inner_iters = g.inner_iters;
+  a.omega_scale = g.omega_scale;
+  a.w_obj = w_obj;
+  return a;
+}
+
+opf_status tape_check(opf_ctx* c) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (c->batch) return fail(c, OPF_E_INVALID, "the adjoint supports one instance, not a batch");
+  if (c->bf16_duals) return fail(c, OPF_E_INVALID, "the adjoint needs FP32 or FP64 duals, not BF16");
+  if (c->opt.inner_iters > kMaxAdjInner)
+    return fail(c, OPF_E_INVALID, "the adjoint supports inner_iters <= 32");
+  return OPF_OK;
+}
+
+template <typename R>
+opf_status tape_forward(opf_ctx* c, int M, int C) {
+  const Inst& s = c->inst[0];
+  TapePlan& t = c->tape;
+  opf_status st = reset_state(c);
+  if (st != OPF_OK) return st;
+  // run exactly M iterations: no stop on convergence or iteration limit
+  st = read_ctls(c);
+  if (st != OPF_OK) return st;
+  c->h_ctl[0].min_iter = INT32_MAX;
+  c->h_ctl[0].max_iter = INT32_MAX;
+  HIP_TRY(c, hipMemcpyAsync(s.ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
+  for (int i = 0; i < M; ++i) {
+    HIP_TRY(c, hipMemcpyAsync(hist + i, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
+    if (i % C == 0) snapshot<R>(c, s, i & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true);
+    enqueue_n(c, 1, false, i);
+  }
+  HIP_TRY(c, hipMemcpyAsync(hist + M, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
+  snapshot<R>(c, s, M & 1, tape_ptr(c, t.final_snap), true);
+  HIP_TRY(c, hipGetLastError());
+  c->tape_hist.assign(size_t(M) + 1, Ctl{});
+  HIP_TRY(c, hipMemcpyAsync(c->tape_hist.data(), hist, sizeof(Ctl) * (size_t(M) + 1),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->host_iter = M;
+  for (int i = 0; i <= M; ++i) {
+    const Ctl& h = c->tape_hist[i];
+    if (h.numeric_bad) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
+    if (h.iter != i || h.cur != (i & 1))
+      return fail(c, OPF_E_STATE, "forward run did not advance one iteration per step");
+  }
+  t.ready = true;
+  return OPF_OK;
+}
+
+template <typename R>
+opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_load,
+                   double* grad_cap, double* grad_pmax) {
+  const Inst& s = c->inst[0];
+  TapePlan& t = c->tape;
+  const int M = t.n_iters, C = t.every;
+  HIP_TRY(c, hipMemsetAsync(tape_ptr(c, t.adj_begin), 0, t.adj_end - t.adj_begin, c->stream));
+  int ob = 0;
+  {
+    AdjArgs<R> a = adj_args<R>(c, s, tape_ptr(c, t.final_snap), ob, w_obj);
+    launch_adj_init<R>(a, cot, c->stream);
+  }
+  Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
+  for (int seg = int(t.n_ckpt) - 1; seg >= 0; --seg) {
+    const int i0 = seg * C, i1 = std::min(M, i0 + C);
+    // recompute the segment from its checkpoint, keeping every iterate
+    snapshot<R>(c, s, i0 & 1, tape_ptr(c, t.ckpt + t.snap.total * seg), false);
+    HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + i0, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
+    for (int i = i0; i < i1; ++i) {
+      snapshot<R>(c, s, i & 1, tape_ptr(c, t.seg + t.snap.total * (i - i0)), true);
+      if (i + 1 < i1) enqueue_n(c, 1, false, i);
+    }
+    for (int i = i1 - 1; i >= i0; --i) {
+      AdjArgs<R> a = adj_args<R>(c, s, tape_ptr(c, t.seg + t.snap.total * (i - i0)), ob, w_obj);
+      const Ctl& h = c->tape_hist[i];
+      a.s.rp = h.rho_p;
+      a.s.rt = h.rho_th;
+      a.s.su = h.su;
+      a.s.sv = h.sv;
+      a.s.su_next = c->tape_hist[i + 1].su;
+      a.s.last = i == M - 1;
+      launch_adj_iteration<R>(a, c->stream);
+      ob ^= 1;
+    }
+    HIP_TRY(c, hipGetLastError());
+  }
+  AdjArgs<R> a = adj_args<R>(c, s, tape_ptr(c, t.final_snap), ob, w_obj);
+  if (grad_cap) launch_adj_cap<R>(a, grad_cap, c->stream);
+  if (grad_load && s.D > 0)
+    HIP_TRY(c, hipMemcpyAsync(grad_load, a.gload, sizeof(double) * s.D * s.T,
+                              hipMemcpyDeviceToDevice, c->stream));
+  if (grad_pmax && s.G > 0)
+    HIP_TRY(c, hipMemcpyAsync(grad_pmax, a.gpmax, sizeof(double) * s.G * s.T,
+                              hipMemcpyDeviceToDevice, c->stream));
+  // leave the iterate where the forward run left it
+  snapshot<R>(c, s, M & 1, tape_ptr(c, t.final_snap), false);
+  HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + M, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->host_iter = M;
+  return OPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Iterate export/import (warm start) and layout queries.
+
+struct BlobHead {
+  char magic[8];
+  int32_t version, precision, N, T, K, L, Jnc, nR, B;
+  double rho_p, rho_th;
+  double su, sv;  // pending rescale ratios (deferred to the next iteration)
+};
+constexpr size_t kBlobHead = 256;
+static_assert(sizeof(BlobHead) <= kBlobHead, "blob header");
+
+template <typename R>
+void state_copy(opf_ctx* c, const Inst& s, int cur, char* blob, bool to_blob,
+                const SnapLayout& sl) {
+  char* arr[kSnapArrays];
+  state_arrays<R>(inst_state<R>(s), cur, arr);
+  for (int i = 0; i < kSnapArrays; ++i) {
+    if (sl.bytes[i] == 0) continue;
+    char* b = blob + kBlobHead + sl.off[i];
+    (void)hipMemcpyAsync(to_blob ? b : arr[i], to_blob ? arr[i] : b, sl.bytes[i],
+                         hipMemcpyDefault, c->stream);
+  }
+}
+
+opf_status state_check(opf_ctx* c) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (c->batch) return fail(c, OPF_E_INVALID, "state export/import is per single instance");
+  if (c->bf16_duals) return fail(c, OPF_E_INVALID, "state export/import needs FP32 or FP64 duals");
+  return OPF_OK;
 }
 
 }  // namespace
@@ -1256,6 +1587,173 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
   best.from_cache = cached ? 1 : 0;
   if (out) *out = best;
   return OPF_OK;
+}
+
+opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
+  opf_status s = check_inst(c, instance);
+  if (s != OPF_OK) return s;
+  if (!out) return fail(c, OPF_E_INVALID, "out is NULL");
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  const Inst& x = c->inst[instance];
+  const int cur = c->h_ctl[instance].cur;
+  std::memset(out, 0, sizeof(*out));
+  out->N = x.N;
+  out->T = x.T;
+  out->K = x.K;
+  out->Kpp = x.Kpp;
+  out->L = x.L;
+  out->Jnc = x.Jnc;
+  out->state_dtype = c->precision == 0 ? OPF_F64 : OPF_F32;
+  out->dual_dtype = c->precision == 0 ? OPF_F64 : (c->bf16_duals ? OPF_BF16 : OPF_F32);
+  auto off = [&](const void* p) { return size_t(static_cast<const char*>(p) - c->ws); };
+  auto fill = [&](const auto& st) {
+    const auto& b = st.buf[cur];
+    out->P = off(b.P);
+    out->Tm = off(b.Tm);
+    out->V1 = off(b.V1);
+    out->V2 = off(b.V2);
+    out->Td = off(b.Td);
+    out->U = off(b.U);
+    out->W = off(b.W);
+    out->TB = off(b.TB);
+    out->pnc = off(st.pnc);
+    out->thnc = off(st.thnc);
+    out->vbar = off(st.vbar);
+  };
+  if (c->precision == 0)
+    fill(x.st64);
+  else if (c->bf16_duals)
+    fill(x.st32b);
+  else
+    fill(x.st32);
+  return OPF_OK;
+}
+
+opf_status opf_state_size(opf_ctx* c, size_t* bytes) {
+  opf_status s = state_check(c);
+  if (s != OPF_OK) return s;
+  if (!bytes) return fail(c, OPF_E_INVALID, "bytes is NULL");
+  *bytes = kBlobHead + snap_layout(c->inst[0], c->precision).total;
+  return OPF_OK;
+}
+
+opf_status opf_get_state(opf_ctx* c, void* dst, size_t bytes) {
+  size_t need = 0;
+  opf_status s = opf_state_size(c, &need);
+  if (s != OPF_OK) return s;
+  if (!dst) return fail(c, OPF_E_INVALID, "dst is NULL");
+  if (bytes < need) return fail(c, OPF_E_INVALID, "dst too small: need " + std::to_string(need));
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  const Inst& x = c->inst[0];
+  const Ctl& h = c->h_ctl[0];
+  BlobHead hd{};
+  std::memcpy(hd.magic, "OPFSTATE", 8);
+  hd.version = 1;
+  hd.precision = c->precision;
+  hd.N = x.N;
+  hd.T = x.T;
+  hd.K = x.K;
+  hd.L = x.L;
+  hd.Jnc = x.Jnc;
+  hd.nR = x.nR;
+  hd.B = x.B;
+  hd.rho_p = h.rho_p;
+  hd.rho_th = h.rho_th;
+  hd.su = h.su;
+  hd.sv = h.sv;
+  char* blob = static_cast<char*>(dst);
+  HIP_TRY(c, hipMemcpyAsync(blob, &hd, sizeof(hd), hipMemcpyDefault, c->stream));
+  const SnapLayout sl = snap_layout(x, c->precision);
+  if (c->precision == 0)
+    state_copy<double>(c, x, h.cur, blob, true, sl);
+  else
+    state_copy<float>(c, x, h.cur, blob, true, sl);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return OPF_OK;
+}
+
+opf_status opf_set_state(opf_ctx* c, const void* src, size_t bytes) {
+  opf_status s = state_check(c);
+  if (s != OPF_OK) return s;
+  if (!src) return fail(c, OPF_E_INVALID, "src is NULL");
+  if (bytes < kBlobHead) return fail(c, OPF_E_INVALID, "state too small");
+  BlobHead hd{};
+  HIP_TRY(c, hipMemcpy(&hd, src, sizeof(hd), hipMemcpyDefault));
+  const Inst& x = c->inst[0];
+  if (std::memcmp(hd.magic, "OPFSTATE", 8) != 0 || hd.version != 1)
+    return fail(c, OPF_E_INVALID, "not a state exported by opf_get_state");
+  if (hd.N != x.N || hd.T != x.T || hd.K != x.K || hd.L != x.L || hd.Jnc != x.Jnc ||
+      hd.nR != x.nR || hd.B != x.B)
+    return fail(c, OPF_E_INVALID, "state was exported from a network of another shape");
+  if (!(hd.precision == 0 ? c->has64 : c->has32))
+    return fail(c, OPF_E_INVALID, "state precision is not held by this context");
+  if (!(hd.rho_p > 0.0 && hd.rho_th > 0.0 && std::isfinite(hd.rho_p) && std::isfinite(hd.rho_th) &&
+        hd.su > 0.0 && hd.sv > 0.0 && std::isfinite(hd.su) && std::isfinite(hd.sv)))
+    return fail(c, OPF_E_INVALID, "state penalties are not positive");
+  const SnapLayout sl = snap_layout(x, hd.precision);
+  if (bytes < kBlobHead + sl.total)
+    return fail(c, OPF_E_INVALID, "state too small: need " + std::to_string(kBlobHead + sl.total));
+  s = reset_state(c);
+  if (s != OPF_OK) return s;
+  char* blob = const_cast<char*>(static_cast<const char*>(src));
+  if (hd.precision == 0)
+    state_copy<double>(c, x, 0, blob, false, sl);
+  else
+    state_copy<float>(c, x, 0, blob, false, sl);
+  Ctl& h = c->h_ctl[0];
+  h.rho_p = hd.rho_p;
+  h.rho_th = hd.rho_th;
+  h.su = hd.su;
+  h.sv = hd.sv;
+  h.precision = hd.precision;
+  HIP_TRY(c, hipMemcpyAsync(x.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->precision = hd.precision;
+  return OPF_OK;
+}
+
+opf_status opf_tape_workspace_size(opf_ctx* c, int32_t n_iters, int32_t checkpoint_every,
+                                   size_t* bytes) {
+  opf_status s = tape_check(c);
+  if (s != OPF_OK) return s;
+  if (!bytes) return fail(c, OPF_E_INVALID, "bytes is NULL");
+  if (n_iters < 1 || checkpoint_every < 1)
+    return fail(c, OPF_E_INVALID, "need n_iters >= 1 and checkpoint_every >= 1");
+  *bytes = plan_tape(c->inst[0], c->has32 ? 1 : 0, n_iters, checkpoint_every).total;
+  return OPF_OK;
+}
+
+opf_status opf_tape_forward(opf_ctx* c, int32_t n_iters, int32_t checkpoint_every,
+                            void* d_tape, size_t bytes) {
+  size_t need = 0;
+  opf_status s = opf_tape_workspace_size(c, n_iters, checkpoint_every, &need);
+  if (s != OPF_OK) return s;
+  if (!d_tape) return fail(c, OPF_E_INVALID, "tape workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_tape) % kAlign != 0)
+    return fail(c, OPF_E_INVALID, "tape workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(c, OPF_E_INVALID, "tape workspace too small: need " + std::to_string(need));
+  // the run starts from the zero iterate in the configured state precision
+  c->tape = plan_tape(c->inst[0], c->has32 ? 1 : 0, n_iters, checkpoint_every);
+  c->tape.base = static_cast<char*>(d_tape);
+  c->tape.bytes = bytes;
+  return c->tape.precision == 0 ? tape_forward<double>(c, n_iters, checkpoint_every)
+                                : tape_forward<float>(c, n_iters, checkpoint_every);
+}
+
+opf_status opf_adjoint(opf_ctx* c, const double* d_cot_power, double cot_objective,
+                       double* d_grad_load, double* d_grad_cap, double* d_grad_pmax) {
+  opf_status s = tape_check(c);
+  if (s != OPF_OK) return s;
+  if (!c->tape.ready) return fail(c, OPF_E_STATE, "no tape: call opf_tape_forward first");
+  if (!std::isfinite(cot_objective)) return fail(c, OPF_E_INVALID, "cot_objective not finite");
+  return c->tape.precision == 0
+             ? adjoint<double>(c, d_cot_power, cot_objective, d_grad_load, d_grad_cap, d_grad_pmax)
+             : adjoint<float>(c, d_cot_power, cot_objective, d_grad_load, d_grad_cap, d_grad_pmax);
 }
 
 const char* opf_last_error(opf_ctx* c) {

@@ -26,6 +26,7 @@ namespace opf {
 constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kRing = 4096;      // residual records kept on the device
+constexpr int kMaxAdjInner = 32; // inner iterations the adjoint's clip recorder holds
 
 struct bf16_t {
   uint16_t u;
@@ -169,6 +170,85 @@ template <typename R, typename VT>
 void launch_batch_iter_rescale(const BatchTab& tab, hipStream_t s);
 template <typename R, typename VT>
 int sweep_batch_resident_blocks();
+// ---------------------------------------------------------------------------
+// Reverse mode (adjoint) of unrolled iterations.  The penalty schedule of the
+// forward run is held fixed; every step of an iteration is piecewise linear
+// in the iterate and in the parameters (load demand, line capacity), so the
+// reverse pass needs only the forward iterate at the start of each iteration
+// (to recover which clips were active).
+
+// Adjoint of the double-buffered part of the iterate (same layout as Buf).
+template <typename R>
+struct AdjBuf {
+  R* P;
+  R* Tm;
+  R* V1;
+  R* V2;
+  R* Td;
+  R* U;
+  R* W;
+  R* TB;
+};
+
+// Scalars of one recorded iteration.
+struct AdjStep {
+  double rp, rt;   // penalties used by the iteration
+  double su, sv;   // pending ratios applied at its start (inner duals, phase duals)
+  double su_next;  // ratio applied to U at its end (1 if the penalty did not change)
+  int32_t last;    // 1 for the last unrolled iteration
+};
+
+template <typename R>
+struct AdjArgs {
+  Topo tp;
+  // forward iterate at the start of the iteration (a snapshot)
+  Buf<R, R> A;
+  const R* avgW;
+  const R* avgTB;
+  const R* pnc;
+  const R* thnc;
+  const R* vbar;
+  const R* ramp_st;
+  const R* bat_st;
+  // adjoint of the iterate after the iteration (read) and before it (written)
+  AdjBuf<R> out, in;
+  R* gsp;      // [N][T] sum over k of the node power-average adjoint (sweep -> devices)
+  R* gsb;      // [N][T] same for the phase average
+  R* avw;      // [N][T] adjoint of the contingency means of W read by the next iteration
+  R* avt;      // [N][T] same for thetabar
+  R* dev_p;    // [Jnc][T] adjoint carried for the device powers
+  R* dev_th;   // [Jnc][T] device phases
+  R* dev_v;    // [Jnc][T] contingency-averaged device phase duals
+  R* dev_x;    // [Jnc][T] adjoint of the prox target of each device
+  R* dev_t;    // [Jnc][T] each device's share of the thetabar-mean adjoint
+  R* ramp_adj; // adjoint of the inner state, same layout as ramp_st
+  R* bat_adj;  // same for bat_st
+  double* gcap;   // [T][L][Kpp] accumulated derivative w.r.t. the line capacities
+  double* gload;  // [D][T] accumulated derivative w.r.t. the load demand
+  double* gpmax;  // [G][T] accumulated derivative w.r.t. the generator upper limits
+  AdjStep s;
+  int32_t nv, lanes_per_row, inner_iters;
+  int64_t n_grps;
+  double omega_scale;
+  double w_obj;   // weight of the objective in the cotangent
+};
+
+// Copy of up to 16 device arrays in one launch (snapshots of the iterate).
+struct CopyList {
+  const char* src[16];
+  char* dst[16];
+  size_t bytes[16];
+  int32_t n;
+};
+
+template <typename R>
+void launch_adj_iteration(const AdjArgs<R>& a, hipStream_t s);
+template <typename R>
+void launch_adj_init(const AdjArgs<R>& a, const double* cot_pnc, hipStream_t s);
+template <typename R>
+void launch_adj_cap(const AdjArgs<R>& a, double* grad_cap, hipStream_t s);
+void launch_copy(const CopyList& cl, hipStream_t s);
+
 // Widening copy of a FP32 iterate into a FP64 iterate (polishing).
 template <typename VT>
 void launch_widen(const KArgs<float, VT>& src, const KArgs<double, double>& dst, hipStream_t s);

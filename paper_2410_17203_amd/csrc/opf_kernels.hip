@@ -20,432 +20,9 @@
 //
 // The path is sparse and elementwise (no dense contraction), so it runs on
 // the vector ALUs and is bound by HBM bandwidth.
-#include "opf_internal.h"
-
-// 1: rows read once per sweep (own price row) and all rows written by it use
-// non-temporal loads and stores, so they do not evict from L2 the line and
-// node rows that neighbouring nodes read again shortly after.
-#ifndef OPF_NT
-#define OPF_NT 1
-#endif
-// Line terminals of a node taken per step of the sweep (1 or 2): all loads of
-// a step are issued before any of them is used.
-#ifndef OPF_SWEEP_BATCH
-#define OPF_SWEEP_BATCH 1
-#endif
-// Minimum waves per SIMD requested for the sweep (0: compiler's choice); a
-// higher value caps its registers so that more waves hide memory latency.
-#ifndef OPF_SWEEP_WAVES
-#define OPF_SWEEP_WAVES 0
-#endif
-#if OPF_SWEEP_WAVES > 0
-#define OPF_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(OPF_SWEEP_WAVES)))
-#else
-#define OPF_SWEEP_ATTR
-#endif
+#include "opf_device.h"
 
 namespace opf {
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N) Vec {
-  T x[N];
-};
-
-// Storage conversion of the phase duals (FP32 arithmetic on BF16 storage).
-template <typename VT, typename R>
-struct DIO;
-template <typename R>
-struct DIO<R, R> {
-  __device__ static R in(R v) { return v; }
-  __device__ static R out(R v) { return v; }
-};
-template <>
-struct DIO<bf16_t, float> {
-  __device__ static float in(bf16_t v) { return __uint_as_float(uint32_t(v.u) << 16); }
-  __device__ static bf16_t out(float f) {
-    uint32_t u = __float_as_uint(f);
-    bf16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      r.u = uint16_t((u >> 16) | 0x40u);
-      return r;
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    r.u = uint16_t(u >> 16);
-    return r;
-  }
-};
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-// 16- or 8-byte vector load/store that bypasses L2 retention when OPF_NT.
-template <typename V>
-__device__ inline V ld_stream(const V* p) {
-  static_assert(sizeof(V) == 16 || sizeof(V) == 8, "vector size");
-#if OPF_NT
-  if constexpr (sizeof(V) == 16) {
-    return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
-  } else {
-    return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p)));
-  }
-#else
-  return *p;
-#endif
-}
-template <typename V>
-__device__ inline void st_stream(V* p, const V& v) {
-  static_assert(sizeof(V) == 16 || sizeof(V) == 8, "vector size");
-#if OPF_NT
-  if constexpr (sizeof(V) == 16) {
-    __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(p));
-  } else {
-    __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2*>(p));
-  }
-#else
-  *p = v;
-#endif
-}
-
-template <typename R>
-__device__ inline R clampv(R x, R lo, R hi) {
-  return x < lo ? lo : (x > hi ? hi : x);
-}
-
-// Workgroups are dealt to the 8 XCDs round-robin by id.  Work items [0, n)
-// are split into 8 contiguous ranges, one per XCD, and the nb/8 blocks of an
-// XCD sweep their range together as one moving front (block j of the XCD
-// takes items j, j + nb/8, ...), so the line and node rows that neighbouring
-// items share are reused from that XCD's L2 shortly after first use.  nb must
-// be a multiple of 8.
-struct Sweep {
-  int64_t first, end;
-  int step;
-};
-#ifndef OPF_XCD_SWEEP
-#define OPF_XCD_SWEEP 1
-#endif
-__device__ inline Sweep xcd_sweep(int b, int nb, int64_t n) {
-  Sweep s;
-#if OPF_XCD_SWEEP
-  const int x = b & 7, j = b >> 3, per = nb >> 3;
-  s.first = n * x / 8 + j;
-  s.end = n * (x + 1) / 8;
-  s.step = per;
-#else
-  s.first = b;
-  s.end = n;
-  s.step = nb;
-#endif
-  return s;
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-// Deterministic block sum; the result is valid in thread 0.
-__device__ inline double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / kWave; ++i) r += sh[i];
-  __syncthreads();
-  return r;
-}
-
-// ---------------------------------------------------------------------------
-// Wavefront linear recurrences.  Element t of a length-T sequence lives in
-// lane t / E, slot t % E.  fwd: x_t = a_t x_{t-1} + b_t with x_{-1} = 0;
-// bwd: x_t = a_t x_{t+1} + b_t with x_T = 0.  Padding slots must hold the
-// identity map (a = 1, b = 0).  The result overwrites b.
-
-template <typename R, int E>
-__device__ inline void scan_fwd(const R (&a)[E], R (&b)[E], int lane) {
-  R A = R(1), B = R(0);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    B = a[e] * B + b[e];
-    A = a[e] * A;
-  }
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const R pA = __shfl_up(A, d);
-    const R pB = __shfl_up(B, d);
-    if (lane >= d) {
-      B = A * pB + B;
-      A = A * pA;
-    }
-  }
-  R x = __shfl_up(B, 1);
-  if (lane == 0) x = R(0);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    x = a[e] * x + b[e];
-    b[e] = x;
-  }
-}
-
-template <typename R, int E>
-__device__ inline void scan_bwd(const R (&a)[E], R (&b)[E], int lane) {
-  R A = R(1), B = R(0);
-#pragma unroll
-  for (int e = E - 1; e >= 0; --e) {
-    B = a[e] * B + b[e];
-    A = a[e] * A;
-  }
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const R pA = __shfl_down(A, d);
-    const R pB = __shfl_down(B, d);
-    if (lane + d < kWave) {
-      B = A * pB + B;
-      A = A * pA;
-    }
-  }
-  R x = __shfl_down(B, 1);
-  if (lane == kWave - 1) x = R(0);
-#pragma unroll
-  for (int e = E - 1; e >= 0; --e) {
-    x = a[e] * x + b[e];
-    b[e] = x;
-  }
-}
-
-// Thomas factors of a tridiagonal matrix with diagonal diag(t) and constant
-// off-diagonal eo: mul_t = eo / m_{t-1}, inv_m_t = 1 / m_t for this lane's
-// slots (each lane runs the pivot recurrence up to its last slot).
-template <typename R, int E, typename Diag>
-__device__ inline void thomas_factors(int T, R eo, Diag diag, int lane, R (&mul)[E], R (&invm)[E]) {
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    mul[e] = R(0);
-    invm[e] = R(0);
-  }
-  const int t0 = lane * E;
-  const int tend = min(T, t0 + E);
-  R mprev = R(1);
-  for (int t = 0; t < tend; ++t) {
-    const R mu = (t == 0) ? R(0) : eo / mprev;
-    const R m = diag(t) - mu * eo;
-    if (t >= t0) {
-      mul[t - t0] = mu;
-      invm[t - t0] = R(1) / m;
-    }
-    mprev = m;
-  }
-}
-
-// Solves the tridiagonal system whose factors come from thomas_factors;
-// rhs in x on entry, solution in x on exit.
-template <typename R, int E>
-__device__ inline void thomas_solve(int T, R eo, const R (&mul)[E], const R (&invm)[E],
-                                    R (&x)[E], int lane) {
-  R a[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const bool ok = lane * E + e < T;
-    a[e] = ok ? -mul[e] : R(1);
-    if (!ok) x[e] = R(0);
-  }
-  scan_fwd<R, E>(a, x, lane);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const bool ok = lane * E + e < T;
-    a[e] = ok ? -eo * invm[e] : R(1);
-    x[e] = ok ? invm[e] * x[e] : R(0);
-  }
-  scan_bwd<R, E>(a, x, lane);
-}
-
-// Value of slot e's predecessor (t - 1) and successor (t + 1) in the wave.
-template <typename R, int E>
-__device__ inline R prev_slot(const R (&v)[E], int e) {
-  R up = __shfl_up(v[E - 1], 1);
-  if ((threadIdx.x & 63) == 0) up = R(0);
-  return e > 0 ? v[e > 0 ? e - 1 : 0] : up;
-}
-template <typename R, int E>
-__device__ inline R next_slot(const R (&v)[E], int e) {
-  R dn = __shfl_down(v[0], 1);
-  if ((threadIdx.x & 63) == kWave - 1) dn = R(0);
-  return e < E - 1 ? v[e < E - 1 ? e + 1 : 0] : dn;
-}
-
-// ---------------------------------------------------------------------------
-// Step 2 for time-coupled devices: inner ADMM (Appendix D) with the device
-// equalities in the x-update and the bounds split off (penalty omega).
-
-// Ramp-limited generator: min c2|p|^2 + c1'p + rho_hat/2 |p - X|^2 over
-// pmin <= p <= pmax, |p_{t+1} - p_t| <= Rl.  x-update matrix
-// (2 c2 + rho_hat + omega) I + omega D'D, tridiagonal.
-template <typename R, int E>
-__device__ void ramp_prox(const Topo& tp, R* st, int r, int g, const R (&X)[E], R rho_hat,
-                          R omega, R su, int n_inner, int lane, R (&p)[E]) {
-  const int T = tp.T;
-  const size_t nRT = size_t(tp.nR) * T;
-  R* bb = st + 0 * nRT + size_t(r) * T;
-  R* lb = st + 1 * nRT + size_t(r) * T;
-  R* br = st + 2 * nRT + size_t(r) * T;
-  R* lr = st + 3 * nRT + size_t(r) * T;
-  const R c2 = R(tp.gen_c2[g]), c1 = R(tp.gen_c1[g]), Rl = R(tp.gen_ramp[g]);
-  const R w = R(2) * c2 + rho_hat;
-  R Bb[E], Lb[E], Br[E], Lr[E], lo[E], hi[E], base[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int t = lane * E + e;
-    if (t < T) {
-      Bb[e] = bb[t];
-      Lb[e] = su * lb[t];
-      Br[e] = (t < T - 1) ? br[t] : R(0);
-      Lr[e] = (t < T - 1) ? su * lr[t] : R(0);
-      lo[e] = R(tp.gen_pmin[size_t(g) * T + t]);
-      hi[e] = R(tp.gen_pmax[size_t(g) * T + t]);
-      base[e] = rho_hat * X[e] - c1;
-    } else {
-      Bb[e] = Lb[e] = Br[e] = Lr[e] = lo[e] = hi[e] = base[e] = R(0);
-    }
-  }
-  const R eo = -omega;
-  R mul[E], invm[E];
-  thomas_factors<R, E>(T, eo, [&](int t) { return w + omega + omega * R((t > 0) + (t < T - 1)); },
-                       lane, mul, invm);
-  R x[E];
-  for (int it = 0; it < n_inner; ++it) {
-    R qr[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) qr[e] = Br[e] - Lr[e];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const R qprev = prev_slot<R, E>(qr, e);
-      x[e] = base[e] + omega * ((Bb[e] - Lb[e]) + qprev - qr[e]);
-    }
-    thomas_solve<R, E>(T, eo, mul, invm, x, lane);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int t = lane * E + e;
-      const R xn = next_slot<R, E>(x, e);
-      if (t < T) {
-        const R bnew = clampv(x[e] + Lb[e], lo[e], hi[e]);
-        Lb[e] += x[e] - bnew;
-        Bb[e] = bnew;
-      }
-      if (t < T - 1) {
-        const R dp = xn - x[e];
-        const R rnew = clampv(dp + Lr[e], -Rl, Rl);
-        Lr[e] += dp - rnew;
-        Br[e] = rnew;
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int t = lane * E + e;
-    p[e] = x[e];
-    if (t < T) {
-      bb[t] = Bb[e];
-      lb[t] = Lb[e];
-      br[t] = Br[e];
-      lr[t] = Lr[e];
-    }
-  }
-}
-
-// Battery: min alpha 1'delta + rho_hat/2 |delta - c - X|^2 subject to
-// s_{t+1} = s_t + eta c_t - delta_t, s_0 = s_T = 0, and bounds on c, delta,
-// s_1..s_{T-1}.  Eliminating (c, delta) per period leaves a tridiagonal
-// system in the dynamics multipliers nu.
-template <typename R, int E>
-__device__ void battery_prox(const Topo& tp, R* st, int b, const R (&X)[E], R rho_hat, R omega,
-                             R su, int n_inner, int lane, R (&p)[E], double& obj) {
-  const int T = tp.T;
-  const size_t nBT = size_t(tp.B) * T;
-  R* arr[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) arr[q] = st + q * nBT + size_t(b) * T;
-  const R Pc = R(tp.bat_P[b]);
-  const R smax = R(tp.bat_dur[b]) * Pc;
-  const R eta = R(tp.bat_eta[b]);
-  const R alpha = R(tp.bat_alpha[b]);
-  const R det = omega * (R(2) * rho_hat + omega);
-  const R h11 = (rho_hat + omega) / det, h12 = rho_hat / det;
-  const R hgc = h11 * eta - h12, hgd = h12 * eta - h11;  // H^-1 g, g = (eta, -1)
-  const R kappa = eta * hgc - hgd;                         // g' H^-1 g
-  const R iw = R(1) / omega;
-  R Bc[E], Lc[E], Bd[E], Ld[E], Bs[E], Ls[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int t = lane * E + e;
-    const bool ok = t < T, oks = t >= 1 && t < T;
-    Bc[e] = ok ? arr[0][t] : R(0);
-    Lc[e] = ok ? su * arr[1][t] : R(0);
-    Bd[e] = ok ? arr[2][t] : R(0);
-    Ld[e] = ok ? su * arr[3][t] : R(0);
-    Bs[e] = oks ? arr[4][t] : R(0);
-    Ls[e] = oks ? su * arr[5][t] : R(0);
-  }
-  R mul[E], invm[E];
-  const R eo = -iw;
-  thomas_factors<R, E>(T, eo, [&](int t) { return kappa + iw * R((t < T - 1) + (t > 0)); }, lane,
-                       mul, invm);
-  R c[E], dl[E];
-  for (int it = 0; it < n_inner; ++it) {
-    R qs[E], nu[E], hrc[E], hrd[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) qs[e] = Bs[e] - Ls[e];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int t = lane * E + e;
-      const R rc = omega * (Bc[e] - Lc[e]) - rho_hat * X[e];
-      const R rd = omega * (Bd[e] - Ld[e]) + rho_hat * X[e] - alpha;
-      hrc[e] = h11 * rc + h12 * rd;
-      hrd[e] = h12 * rc + h11 * rd;
-      const R qn = next_slot<R, E>(qs, e);
-      nu[e] = (t < T - 1 ? qn : R(0)) - qs[e] - (eta * hrc[e] - hrd[e]);
-    }
-    thomas_solve<R, E>(T, eo, mul, invm, nu, lane);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int t = lane * E + e;
-      const R np = prev_slot<R, E>(nu, e);
-      c[e] = hrc[e] + nu[e] * hgc;
-      dl[e] = hrd[e] + nu[e] * hgd;
-      if (t < T) {
-        R nb = clampv(c[e] + Lc[e], R(0), Pc);
-        Lc[e] += c[e] - nb;
-        Bc[e] = nb;
-        nb = clampv(dl[e] + Ld[e], R(0), Pc);
-        Ld[e] += dl[e] - nb;
-        Bd[e] = nb;
-      }
-      if (t >= 1 && t < T) {
-        const R s = qs[e] + (nu[e] - np) * iw;
-        const R nb = clampv(s + Ls[e], R(0), smax);
-        Ls[e] += s - nb;
-        Bs[e] = nb;
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int t = lane * E + e;
-    p[e] = dl[e] - c[e];
-    if (t < T) {
-      obj += double(alpha) * double(dl[e]);
-      arr[0][t] = Bc[e];
-      arr[1][t] = Lc[e];
-      arr[2][t] = Bd[e];
-      arr[3][t] = Ld[e];
-      if (t >= 1) {
-        arr[4][t] = Bs[e];
-        arr[5][t] = Ls[e];
-      }
-    }
-  }
-}
 
 // Step 2 for one generator, load or battery (one wavefront, all periods):
 // deferred phase-dual update, theta = avg_k(thetabar - v), then the prox of
@@ -478,16 +55,17 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
     const int r = tp.ramp_idx[j];
     const R c2 = R(tp.gen_c2[j]), c1 = R(tp.gen_c1[j]);
     if (r < 0) {
-      const R den = R(2) * c2 + rho_hat;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int t = lane * E + e;
         if (t < T)
-          pn[e] = clampv((rho_hat * X[e] - c1) / den, R(tp.gen_pmin[size_t(j) * T + t]),
+          pn[e] = clampv(gen_target(X[e], c1, c2, rho_hat), R(tp.gen_pmin[size_t(j) * T + t]),
                          R(tp.gen_pmax[size_t(j) * T + t]));
       }
     } else {
-      ramp_prox<R, E>(tp, a.st.ramp_st, r, j, X, rho_hat, omega, su, a.g.inner_iters, lane, pn);
+      NoMasks nm;
+      ramp_prox<R, E>(tp, a.st.ramp_st, a.st.ramp_st, r, j, X, rho_hat, omega, su, a.g.inner_iters,
+                      lane, pn, nm);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -500,8 +78,9 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
       if (t < T) pn[e] = -R(tp.load_d[size_t(d) * T + t]);
     }
   } else {
-    battery_prox<R, E>(tp, a.st.bat_st, j - tp.G - tp.D, X, rho_hat, omega, su, a.g.inner_iters,
-                       lane, pn, obj);
+    NoMasks nm;
+    battery_prox<R, E>(tp, a.st.bat_st, a.st.bat_st, j - tp.G - tp.D, X, rho_hat, omega, su,
+                       a.g.inner_iters, lane, pn, obj, nm);
   }
   double dp = 0.0;
 #pragma unroll
@@ -517,55 +96,7 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
   acc_obj += obj;
 }
 
-// Step 1 for one line and one 16-byte vector of contingencies (Section 4.2,
-// AC line prox with the per-contingency susceptance and capacity of the N-1
-// model), preceded by the deferred scaled-price update v += theta - thetabar
-// of the previous iteration and the pending penalty rescale.  Both end
-// nodes of a line call this with identical inputs.
-template <typename R, int VEC>
-struct LineOut {
-  R p[VEC], tm[VEC], v1[VEC], v2[VEC], half[VEC];
-};
 
-template <typename R, typename VT, int VEC>
-__device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC>& Tm,
-                                          const Vec<VT, VEC>& V1, const Vec<VT, VEC>& V2,
-                                          const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
-                                          const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
-                                          const Vec<int32_t, VEC>& ok, int l, const R* td_old,
-                                          int k0, int Kp, R s, R cap, R rp, R rt, R sv,
-                                          LineOut<R, VEC>& o) {
-  const R inv2s = R(0.5) / s;
-  const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;  // 2 rho_p + rho_th / (2 s^2)
-  const R ca = rp / den;                                // weight of z2 - z1
-  const R cb = rt * inv2s / den;                        // weight of xi1 - xi2
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) {
-    const bool outg = ok.x[e] == l;
-    const R half = outg ? td_old[e] : P.x[e] * inv2s;
-    const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
-    R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
-    R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
-    const R z1 = -P.x[e] - Wf.x[e];  // ptilde - u at terminal 1 (p1 = -P)
-    const R z2 = P.x[e] - Wh.x[e];   // ptilde - u at terminal 2
-    const R xi1 = Bf.x[e] - v1, xi2 = Bh.x[e] - v2;
-    R tm = R(0.5) * (xi1 + xi2);
-    R pn, hn;
-    if (outg) {
-      pn = R(0);
-      hn = R(0.5) * (xi1 - xi2);
-    } else {
-      pn = clampv(ca * (z2 - z1) + cb * (xi1 - xi2), -cap, cap);
-      hn = pn * inv2s;
-    }
-    if (k0 + e >= Kp) pn = tm = v1 = v2 = hn = R(0);
-    o.p[e] = pn;
-    o.tm[e] = tm;
-    o.v1[e] = v1;
-    o.v2[e] = v2;
-    o.half[e] = hn;
-  }
-}
 
 // Steps 1 and 3 for one (period, node) row and one 16-byte vector of
 // contingencies.  acc: FP64 residual partials [sum |n| pbar^2, sum theta

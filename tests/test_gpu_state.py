@@ -1,0 +1,121 @@
+"""The iterate through the ABI: zero-copy layout views, export and import
+(warm start, Section 3.4)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_17203_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def small(seed=21, **kw):
+    args = dict(N=40, L=56, G=8, D=30, B=3, T=12, K=5, seed=seed)
+    args.update(kw)
+    return synth.make_instance("state", **args)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_layout_views_match_exported_fields(dtype):
+    from paper_2410_17203_amd.binding import Solver
+    say(f"[state] layout views {dtype}")
+    inst = small()
+    s = Solver(inst, dtype=dtype, polish_fp64=0)
+    s.iterate(23)
+    Kp = inst.K + 1
+    P = s.field("P")                         # [K+1, L, T]
+    v = s.view("P").double().cpu()           # [T, L, Kpp]
+    assert torch.equal(v[:, :, :Kp].permute(2, 1, 0), P)
+    U = s.field("U")
+    assert torch.equal(s.view("U").double().cpu()[:, :, :Kp].permute(2, 1, 0), U)
+    assert torch.equal(s.view("pnc").double().cpu(), s.field("PNC"))
+    s.close()
+
+
+@pytest.mark.parametrize("split", [50, 47])
+def test_export_import_continues_bitwise(split):
+    """Stopping after `split` iterations (50: right after a penalty change is
+    decided, with a rescale still pending), exporting, importing into a new
+    context and running on gives the same iterates as running straight on."""
+    from paper_2410_17203_amd.binding import Solver
+    say(f"[state] export/import at {split}")
+    inst = small()
+    opts = dict(rho_p=0.2, rho_theta=4.0, polish_fp64=0)
+    a = Solver(inst, dtype="f64", **opts)
+    a.iterate(split)
+    blob = a.get_state()
+    a.iterate(40)
+    b = Solver(inst, dtype="f64", **opts)
+    if split % 10 == 0:
+        b.set_state(blob)
+        b.iterate(40)
+        for f in ["P", "TH1", "V2", "U", "THBAR", "PNC", "VNC"]:
+            assert torch.equal(a.field(f), b.field(f)), f
+        assert b.residuals()["rho_p"] == a.residuals()["rho_p"]
+    else:
+        # off the penalty-update phase the adaptive schedule shifts; with the
+        # rule off the continuation is still exact
+        c = Solver(inst, dtype="f64", adapt_every=0, **opts)
+        c.iterate(split)
+        blob0 = c.get_state()
+        c.iterate(40)
+        d = Solver(inst, dtype="f64", adapt_every=0, **opts)
+        d.set_state(blob0)
+        d.iterate(40)
+        for f in ["P", "TH1", "V2", "U", "THBAR", "PNC", "VNC"]:
+            assert torch.equal(c.field(f), d.field(f)), f
+        c.close()
+        d.close()
+    a.close()
+    b.close()
+
+
+def test_warm_start_takes_fewer_iterations():
+    """Solve, perturb the loads by a few percent (the next day's forecast),
+    solve again from the previous iterate: fewer iterations than from zero."""
+    from paper_2410_17203_amd.binding import Solver
+    say("[state] warm start")
+    inst = small(seed=5, N=60, L=84, G=12, D=45, B=3, T=12, K=3)
+    s = Solver(inst, dtype="f64", eps=1e-4, max_iter=20000)
+    r0 = s.solve()
+    assert r0["status"] == "OPF_OK"
+    blob = s.get_state()
+    s.close()
+    nxt = synth.make_instance("state", N=60, L=84, G=12, D=45, B=3, T=12, K=3, seed=5)
+    rng = np.random.default_rng(1)
+    nxt.load_d = np.asarray(inst.load_d) * (1.0 + 0.03 * rng.standard_normal(np.shape(inst.load_d)))
+    cold = Solver(nxt, dtype="f64", eps=1e-4, max_iter=20000)
+    rc = cold.solve()
+    warm = Solver(nxt, dtype="f64", eps=1e-4, max_iter=20000)
+    warm.set_state(blob)
+    rw = warm.solve()
+    say(f"  cold {rc['iter']} iterations, warm {rw['iter']} (day 1: {r0['iter']})")
+    assert rc["status"] == rw["status"] == "OPF_OK"
+    assert rw["iter"] < rc["iter"]
+    assert abs(rw["objective"] - rc["objective"]) <= 1e-3 * abs(rc["objective"])
+    cold.close()
+    warm.close()
+
+
+def test_import_rejects_mismatched_state():
+    from paper_2410_17203_amd.binding import OpfError, Solver
+    say("[state] rejects")
+    a = Solver(small(), dtype="f64")
+    a.iterate(3)
+    blob = a.get_state()
+    b = Solver(small(K=4), dtype="f64")
+    with pytest.raises(OpfError, match="another shape"):
+        b.set_state(blob)
+    bad = blob.clone()
+    bad[:8] = 0
+    with pytest.raises(OpfError, match="not a state"):
+        a.set_state(bad)
+    a.close()
+    b.close()
