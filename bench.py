@@ -213,7 +213,8 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_wri
                                            "counter_collection_trace.csv"))
                 if r["Counter_Name"] == counter]
         copy = [float(r["Counter_Value"]) for r in rows if "MulFunctor" in r["Kernel_Name"]]
-        sweep = [float(r["Counter_Value"]) for r in rows if "k_sweep<" in r["Kernel_Name"]]
+        sweep = [float(r["Counter_Value"]) for r in rows
+                 if "k_sweep<" in r["Kernel_Name"] or "k_sweep_tile<" in r["Kernel_Name"]]
         if not copy or not sweep:
             raise RuntimeError(f"{counter}: copy or sweep dispatches missing")
         copy_kib = sum(copy) / len(copy)
@@ -223,7 +224,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_wri
     wr, wcopy, wsweep, nw = per_kernel(write_dir, "WRITE_SIZE")
     read_b = fsweep * 1024 * fr
     write_b = wsweep * 1024 * wr
-    d = {"kernel": "k_sweep", "workload": "large, FP32 iterate",
+    d = {"kernel": "k_sweep_tile", "workload": "large, FP32 iterate",
          "kernel_source_hash": kernel_source_hash(),
          "fetch_kib_per_launch_raw": fsweep, "write_kib_per_launch_raw": wsweep,
          "copy_fetch_kib_raw": fcopy, "copy_write_kib_raw": wcopy,

@@ -244,12 +244,16 @@ opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, op
  * offsets from the workspace start; valid until the next iteration, which
  * flips the double buffer).  Line arrays P (flow at the to end), Tm (mean of
  * the two terminal phases), V1, V2 (scaled phase duals before this
- * iteration's update) are [T][L][Kpp]; Td ([T][Kpp]) is the half phase
- * difference of each contingency's outaged line; node arrays U (scaled
- * price), W (= pbar + U) and TB (thetabar) are [T][N][Kpp]; device arrays
- * pnc, thnc, vbar (contingency mean of the phase duals) are [G+D+B][T].
- * Contingency k < K+1 is innermost, padded to Kpp.  Element types:
- * state_dtype for all but V1, V2 (dual_dtype).  Synchronises. */
+ * iteration's update) are [T][chunk][L][w] and node arrays U (scaled price),
+ * W (= pbar + U) and TB (thetabar) are [T][chunk][N][w]: the K+1
+ * contingencies, padded to Kpp (a multiple of 4), are split into chunks of
+ * 16, chunk c holding contingencies 16c .. 16c + w - 1 with
+ * w = min(16, Kpp - 16c), so element (t, i, k) is at
+ * (t * Kpp + 16 c) * count + i * w + (k - 16 c), c = k / 16.  Td ([T][Kpp])
+ * is the half phase difference of each contingency's outaged line; device
+ * arrays pnc, thnc, vbar (contingency mean of the phase duals) are
+ * [G+D+B][T].  Element types: state_dtype for all but V1, V2 (dual_dtype).
+ * Synchronises. */
 typedef struct {
   int32_t N, T, K, Kpp, L, Jnc;
   int32_t state_dtype, dual_dtype;

@@ -305,22 +305,29 @@ class Solver:
         return {name: getattr(lay, name) for name, _ in lay._fields_}
 
     def view(self, name: str, instance: int = 0):
-        """Zero-copy view of one array of the current iterate in the library's
-        own layout ([T][L][Kpp], [T][N][Kpp] or [Jnc][T]); valid until the
-        next iteration."""
+        """Zero-copy views of one array of the current iterate, valid until
+        the next iteration.  Line and node arrays: a list with one [T, count,
+        w] tensor per chunk of (at most 16) contingencies; Td [T, Kpp];
+        device arrays [Jnc, T]."""
         torch = self.torch
         lay = self.layout(instance)
         dt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
         is_dual = name in ("V1", "V2")
         dtype = dt[lay["dual_dtype"] if is_dual else lay["state_dtype"]]
         T, L, N, Kpp, J = lay["T"], lay["L"], lay["N"], lay["Kpp"], lay["Jnc"]
-        shape = {"P": (T, L, Kpp), "Tm": (T, L, Kpp), "V1": (T, L, Kpp), "V2": (T, L, Kpp),
-                 "Td": (T, Kpp), "U": (T, N, Kpp), "W": (T, N, Kpp), "TB": (T, N, Kpp),
-                 "pnc": (J, T), "thnc": (J, T), "vbar": (J, T)}[name]
         esize = torch.empty((), dtype=dtype).element_size()
-        n = int(np.prod(shape))
-        off = lay[name]
-        return self.ws[off:off + n * esize].view(dtype).view(shape)
+        off = lay[name] // esize
+        if name in ("Td", "pnc", "thnc", "vbar"):
+            shape = (T, Kpp) if name == "Td" else (J, T)
+            n = int(np.prod(shape))
+            return self.ws[lay[name]:lay[name] + n * esize].view(dtype).view(shape)
+        count = L if name in ("P", "Tm", "V1", "V2") else N
+        flat = self.ws.view(dtype) if self.ws.numel() % esize == 0 else None
+        out = []
+        for c0 in range(0, Kpp, 16):
+            w = min(16, Kpp - c0)
+            out.append(flat.as_strided((T, count, w), (Kpp * count, w, 1), off + c0 * count))
+        return out
 
     def get_state(self):
         """The whole iterate and penalties as a uint8 device tensor."""

@@ -76,7 +76,7 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
   const Topo& tp = a.tp;
   const int t = row / tp.N, n = row - t * tp.N;
   const int k0 = v * VEC;
-  const size_t off = size_t(row) * tp.Kpp + k0;
+  const size_t off = ck_off(t, n, k0, tp.N, tp.Kpp);
   const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
   const VR Wo = *reinterpret_cast<const VR*>(a.A.W + off);
   const VR Bo = *reinterpret_cast<const VR*>(a.A.TB + off);
@@ -89,13 +89,12 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
   R accW[VEC], accB[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) accW[e] = accB[e] = R(0);
-  const size_t lrow = size_t(t) * tp.L, nrow = size_t(t) * tp.N;
   for (int q = q0; q < q1; ++q) {
     const int2 term = tp.node_lterm[q];
     const int l = term.x >> 1, m = term.y;
     const bool to_end = term.x & 1;  // this node is the line's terminal-2 node
-    const size_t ol = (lrow + l) * tp.Kpp + k0;
-    const size_t oo = (nrow + m) * tp.Kpp + k0;
+    const size_t ol = ck_off(t, l, k0, tp.L, tp.Kpp);
+    const size_t oo = ck_off(t, m, k0, tp.N, tp.Kpp);
     const VR P = *reinterpret_cast<const VR*>(a.A.P + ol);
     const VR Tm = *reinterpret_cast<const VR*>(a.A.Tm + ol);
     const VR V1 = *reinterpret_cast<const VR*>(a.A.V1 + ol);
@@ -517,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_cap(AdjArgs<R> a, double* grad) 
   const int64_t per = int64_t(tp.T) * tp.Kpp;
   for (int64_t i = threadIdx.x; i < per; i += kBlock) {
     const int t = int(i / tp.Kpp), k = int(i - int64_t(t) * tp.Kpp);
-    s += a.gcap[(size_t(t) * tp.L + l) * tp.Kpp + k];
+    s += a.gcap[ck_off(t, l, k, tp.L, tp.Kpp)];
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) grad[l] = s;

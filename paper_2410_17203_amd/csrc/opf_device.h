@@ -128,6 +128,17 @@ __device__ inline Sweep xcd_sweep(int b, int nb, int64_t n) {
   return s;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full __syncthreads also waits for every
+// outstanding global load and store of the wave).  For phases that exchange
+// data through LDS and never read back global memory written by the
+// workgroup.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ inline double wave_sum(double v) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
   return v;

@@ -106,6 +106,7 @@ struct InstPlan {
       nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
       bat_eta, bat_alpha;
   size_t part_sweep, part_nc;
+  size_t clus_n0, tl_ptr, tl, tcsr;
   StateOffsets o64{}, o32{};
 };
 
@@ -267,7 +268,8 @@ void set_sizes(Inst& s, const opf_network* n) {
 
 // Launch geometry of one instance for 16-byte vectors of `vec` elements;
 // lanes_shift scales the lanes per row (tuning), resident caps the grid.
-void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, Geom& g) {
+void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resident_tile,
+               Geom& g) {
   g.nv = s.Kpp / vec;
   g.n_nc_blocks = (s.Jnc + 3) / 4;
   int lpr = 1;
@@ -285,6 +287,17 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, Geom& g) 
     const int cap = std::min(kMaxSweepBlocks, std::max(8, int(resident * c->grid_factor) / 8 * 8));
     g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
   }
+  g.tile_blocks = 0;
+  // the tiled sweep is used for the FP32 iterate; in FP64 the node-row sweep
+  // measured faster on MI355X (its rows are twice as wide, so each holds more
+  // outstanding loads, and the tile's half-chunk passes re-read lines)
+  if (!c->batch && vec == 4 && s.topo.Q > 0 && resident_tile >= 8) {
+    const int64_t items = int64_t(s.T) * s.topo.Q;
+    const int cap = std::min(kMaxSweepBlocks,
+                             std::max(8, int(resident_tile * c->grid_factor) / 8 * 8));
+    g.tile_blocks = std::max(8, std::min(cap, round8(items)));
+  }
+  g.n_part = g.tile_blocks > 0 ? g.tile_blocks : g.n_sweep_blocks;
   g.inner_iters = c->opt.inner_iters;
   g.omega_scale = c->opt.inner_omega_scale;
 }
@@ -355,6 +368,10 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
   p.node_nptr = L.take((Ni + 1) * 4);
   p.node_nterm = L.take(size_t(s.Jnc) * 4);
   p.deg = L.take(Ni * 8);
+  p.clus_n0 = L.take((Ni + 1) * 4);
+  p.tl_ptr = L.take((Ni + 1) * 4);
+  p.tl = L.take(2 * Li * 16);
+  p.tcsr = L.take(2 * Li * 4);
   p.nc_node = L.take(size_t(s.Jnc) * 4);
   p.ramp_idx = L.take(Gi * 4);
   p.gen_c2 = L.take(Gi * 8);
@@ -546,7 +563,11 @@ opf_status widen_to_fp64(opf_ctx* c) {
 
 // (Re)computes every instance's launch geometry and the batch work lists.
 opf_status refresh_geometry(opf_ctx* c) {
-  int res64 = 0, res32 = 0;
+  int res64 = 0, res32 = 0, tile64 = 0, tile32 = 0;
+  if (!c->batch) {
+    tile64 = tile_resident_blocks<double, double>();
+    tile32 = c->bf16_duals ? tile_resident_blocks<float, bf16_t>() : tile_resident_blocks<float, float>();
+  }
   if (c->batch) {
     res64 = sweep_batch_resident_blocks<double, double>();
     res32 = c->bf16_duals ? sweep_batch_resident_blocks<float, bf16_t>()
@@ -560,7 +581,7 @@ opf_status refresh_geometry(opf_ctx* c) {
     for (int p = 0; p < 2; ++p) {
       Geom& g = p == 0 ? s.geom64 : s.geom32;
       const Geom keep = g;  // scratch pointers are fixed at load
-      make_geom(c, s, p == 0 ? 2 : 4, p == 0 ? res64 : res32, g);
+      make_geom(c, s, p == 0 ? 2 : 4, p == 0 ? res64 : res32, p == 0 ? tile64 : tile32, g);
       g.part_sweep = keep.part_sweep;
       g.part_nc = keep.part_nc;
       g.ctl = keep.ctl;
@@ -717,6 +738,57 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   }
   std::vector<double> deg(N);
   for (int v = 0; v < N; ++v) deg[v] = double(lptr[v + 1] - lptr[v] + nptr[v + 1] - nptr[v]);
+  // Clusters of consecutive nodes for the tiled sweep: at most kTileNodes
+  // nodes and kTileLines distinct incident lines each, sized so that one
+  // iteration has a few thousand (period, cluster) tiles.  Per cluster, the
+  // lines touching it (first occurrence in node and CSR order) with the
+  // cluster-local index of each end inside it and the far node otherwise;
+  // per line terminal, its line's index in that table.
+  std::vector<int32_t> clus_n0(1, 0), tl_ptr(1, 0), tl, tcsr(2 * size_t(L), 0);
+  bool tiles_ok = N > 0;
+  {
+    const int cmax = int(std::min<int64_t>(kTileNodes, std::max<int64_t>(8, int64_t(N) * T / 4096)));
+    std::vector<int32_t> mark(L, -1), pos(L, 0);
+    int n0 = 0;
+    while (tiles_ok && n0 < N) {
+      const int cid = int(clus_n0.size()) - 1;
+      int m = n0, cnt = 0;
+      while (m < N && m - n0 < cmax) {
+        int add = 0;
+        for (int q = lptr[m]; q < lptr[m + 1]; ++q)
+          if (mark[lterm[2 * size_t(q)] >> 1] != cid) ++add;
+        if (cnt + add > kTileLines) break;
+        for (int q = lptr[m]; q < lptr[m + 1]; ++q) mark[lterm[2 * size_t(q)] >> 1] = cid;
+        cnt += add;
+        ++m;
+      }
+      if (m == n0) {  // one node with more lines than a tile holds
+        tiles_ok = false;
+        break;
+      }
+      const int n1 = m;
+      const int base = int(tl.size() / 4);
+      for (int v = n0; v < n1; ++v)
+        for (int q = lptr[v]; q < lptr[v + 1]; ++q) {
+          const int l = lterm[2 * size_t(q)] >> 1, end = lterm[2 * size_t(q)] & 1;
+          if (mark[l] != -2 - cid) {
+            mark[l] = -2 - cid;
+            pos[l] = int(tl.size() / 4) - base;
+            const int f = n->line_from[l], h = n->line_to[l];
+            const bool fin = f >= n0 && f < n1, hin = h >= n0 && h < n1;
+            tl.push_back(l);
+            tl.push_back(fin ? f - n0 : -1);
+            tl.push_back(hin ? h - n0 : -1);
+            tl.push_back(fin && hin ? -1 : (fin ? h : f));
+          }
+          tcsr[q] = 2 * pos[l] + end;
+        }
+      n0 = n1;
+      clus_n0.push_back(n0);
+      tl_ptr.push_back(int(tl.size() / 4));
+    }
+  }
+  s.topo.Q = tiles_ok ? int(clus_n0.size()) - 1 : 0;
   std::vector<int32_t> ramp_idx(G, -1);
   {
     int r = 0;
@@ -742,6 +814,12 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   HIP_TRY(c, up(p.node_nptr, nptr.data(), size_t(N + 1) * 4));
   HIP_TRY(c, up(p.node_nterm, nterm.data(), nterm.size() * 4));
   HIP_TRY(c, up(p.deg, deg.data(), size_t(N) * 8));
+  if (tiles_ok) {
+    HIP_TRY(c, up(p.clus_n0, clus_n0.data(), clus_n0.size() * 4));
+    HIP_TRY(c, up(p.tl_ptr, tl_ptr.data(), tl_ptr.size() * 4));
+    HIP_TRY(c, up(p.tl, tl.data(), tl.size() * 4));
+    HIP_TRY(c, up(p.tcsr, tcsr.data(), tcsr.size() * 4));
+  }
   HIP_TRY(c, up(p.nc_node, nc_node.data(), size_t(Jnc) * 4));
   HIP_TRY(c, up(p.ramp_idx, ramp_idx.data(), size_t(G) * 4));
   HIP_TRY(c, up(p.gen_c2, n->gen_c2, size_t(G) * 8));
@@ -770,6 +848,10 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   tp.node_nptr = reinterpret_cast<const int32_t*>(ws + p.node_nptr);
   tp.node_nterm = reinterpret_cast<const int32_t*>(ws + p.node_nterm);
   tp.deg = reinterpret_cast<const double*>(ws + p.deg);
+  tp.clus_n0 = reinterpret_cast<const int32_t*>(ws + p.clus_n0);
+  tp.tl_ptr = reinterpret_cast<const int32_t*>(ws + p.tl_ptr);
+  tp.tl = reinterpret_cast<const int4*>(ws + p.tl);
+  tp.tcsr = reinterpret_cast<const int32_t*>(ws + p.tcsr);
   tp.nc_node = reinterpret_cast<const int32_t*>(ws + p.nc_node);
   tp.ramp_idx = reinterpret_cast<const int32_t*>(ws + p.ramp_idx);
   tp.gen_c2 = reinterpret_cast<const double*>(ws + p.gen_c2);

@@ -1,16 +1,19 @@
 // Internal device-side data structures of the message-passing library.
 //
 // Data layout in HBM (one instance):
-//   line arrays   [T][L][Kpp]  flow P, mean phase Tm, phase duals V1, V2
-//   node arrays   [T][N][Kpp]  price U, W = pbar + U, thetabar TB
-//   node averages [N][T]       mean over contingencies of W and TB
-//   device arrays [Jnc][T]     generator/load/battery power, phase and the
-//                              contingency-averaged phase dual
-// The contingency index k is innermost (padded to Kpp, a multiple of 4) so
-// that every gather of a node slab by a line, and every line read by a node,
-// is a contiguous run of Kp values.  Time is outermost so that a sweep over
-// one period's nodes touches only that period's line and node slabs.  A
-// line's two phases are stored as their mean Tm; the half difference is
+//   line arrays   [T][chunk][L][w]  flow P, mean phase Tm, phase duals V1, V2
+//   node arrays   [T][chunk][N][w]  price U, W = pbar + U, thetabar TB
+//   node averages [N][T]            mean over contingencies of W and TB
+//   device arrays [Jnc][T]          generator/load/battery power, phase and
+//                                   the contingency-averaged phase dual
+// The K+1 contingencies (padded to Kpp, a multiple of 4) are split into
+// chunks of 16 (the last one w = Kpp - 16 c wide).  Within a chunk the w
+// contingencies of one line or node are contiguous (64 bytes in FP32) and
+// consecutive lines or nodes follow each other, so a tile of neighbouring
+// nodes (or the lines they own) in one period and chunk is one contiguous
+// run of memory, and every 16-byte vector of contingencies lies in one chunk.
+// Time is outermost.  FP32 and FP64 iterates use the same element indices.
+// A line's two phases are stored as their mean Tm; the half difference is
 // P / (2 b) for a live line and, for the one outaged line of contingency k,
 // a separate [T][Kpp] array Td.  Line and node arrays are double-buffered
 // (the sweep reads one buffer and writes the other).
@@ -27,6 +30,23 @@ constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kRing = 4096;      // residual records kept on the device
 constexpr int kMaxAdjInner = 32; // inner iterations the adjoint's clip recorder holds
+constexpr int kChunk = 16;       // contingencies per chunk of the line and node arrays
+#ifndef OPF_TILE_NODES
+#define OPF_TILE_NODES 64
+#endif
+#ifndef OPF_TILE_LINES
+#define OPF_TILE_LINES 128
+#endif
+constexpr int kTileNodes = OPF_TILE_NODES;  // most nodes in one cluster of the tiled sweep
+constexpr int kTileLines = OPF_TILE_LINES;  // most lines touching one cluster
+
+// Element index of contingency k of item i (a line, count = L, or a node,
+// count = N) in period t.
+__host__ __device__ inline size_t ck_off(int t, int i, int k, int count, int Kpp) {
+  const int c0 = k & ~(kChunk - 1);
+  const int w = Kpp - c0 < kChunk ? Kpp - c0 : kChunk;
+  return (size_t(t) * Kpp + c0) * size_t(count) + size_t(i) * w + (k - c0);
+}
 
 struct bf16_t {
   uint16_t u;
@@ -83,6 +103,12 @@ struct Topo {
   const double* bat_dur;
   const double* bat_eta;
   const double* bat_alpha;
+  // clusters of consecutive nodes for the tiled sweep (Q = 0: not used)
+  int32_t Q;
+  const int32_t* clus_n0;     // [Q+1] first node of each cluster
+  const int32_t* tl_ptr;      // [Q+1] range of each cluster's lines in tl
+  const int4* tl;             // (line, local from node or -1, local to node or -1, far node or -1)
+  const int32_t* tcsr;        // parallel to node_lterm: 2 * (index in the cluster's tl) + end
 };
 
 // Double-buffered part of the iterate.
@@ -119,6 +145,8 @@ struct Geom {
   int32_t rows_per_grp;   // rows per block step: 4 waves * (64 / lanes_per_row)
   int64_t n_grps;         // ceil(N*T / rows_per_grp), rows ordered t * N + n
   int32_t n_sweep_blocks; // multiple of 8
+  int32_t tile_blocks;    // grid of the tiled sweep (0: node-row sweep is used)
+  int32_t n_part;         // residual partials written by the active sweep kernel
   int32_t inner_iters;
   double omega_scale;
   double* part_sweep;     // [n_sweep_blocks][5]
@@ -150,6 +178,8 @@ struct BatchTab {
 // Host-side launchers (opf_kernels.hip).
 template <typename R, typename VT>
 int sweep_resident_blocks();
+template <typename R, typename VT>
+int tile_resident_blocks();
 template <typename R, typename VT>
 void launch_devices(const KArgs<R, VT>& a, hipStream_t s);
 template <typename R, typename VT>

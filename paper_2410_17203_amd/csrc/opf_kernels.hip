@@ -113,7 +113,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
   const int T = tp.T;
   const int t = row / tp.N, n = row - t * tp.N;  // row = t * N + n
   const int k0 = v * VEC;
-  const size_t off = size_t(row) * tp.Kpp + k0;
+  const size_t off = ck_off(t, n, k0, tp.N, tp.Kpp);
   const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
   const VR Uo = ld_stream(reinterpret_cast<const VR*>(A.U + off));
   const VR Wo = *reinterpret_cast<const VR*>(A.W + off);
@@ -126,7 +126,6 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
 #pragma unroll
   for (int e = 0; e < VEC; ++e) sp[e] = sb[e] = c[e] = s1[e] = s2[e] = R(0);
   bool first = true;
-  const size_t lrow = size_t(t) * tp.L, nrow = size_t(t) * tp.N;
   constexpr int NB = OPF_SWEEP_BATCH;
   for (int q = q0; q < q1; q += NB) {
     int2 term[NB];
@@ -137,8 +136,8 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       if (term[u].x >= 0) {
-        const size_t ol = (lrow + (term[u].x >> 1)) * tp.Kpp + k0;
-        const size_t oo = (nrow + term[u].y) * tp.Kpp + k0;
+        const size_t ol = ck_off(t, term[u].x >> 1, k0, tp.L, tp.Kpp);
+        const size_t oo = ck_off(t, term[u].y, k0, tp.N, tp.Kpp);
         P[u] = *reinterpret_cast<const VR*>(A.P + ol);
         Tm[u] = *reinterpret_cast<const VR*>(A.Tm + ol);
         V1[u] = *reinterpret_cast<const VV*>(A.V1 + ol);
@@ -152,7 +151,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       if (term[u].x < 0) break;
       const int l = term[u].x >> 1;
       const bool to_end = term[u].x & 1;  // this node is the line's terminal-2 node
-      const size_t ol = (lrow + l) * tp.Kpp + k0;
+      const size_t ol = ck_off(t, l, k0, tp.L, tp.Kpp);
       LineOut<R, VEC> o;
       line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo, to_end ? Wo : Wx[u],
                             to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l, td_old, k0, tp.Kp,
@@ -287,6 +286,232 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled sweep: steps 1 and 3 for one (period, cluster of consecutive nodes)
+// per workgroup, chunk by chunk of 16 contingencies.  The cluster's old W
+// and thetabar rows are staged in LDS; every line touching the cluster is
+// proxed once per cluster (a line with both ends inside is read and computed
+// once; a line cut by the cluster boundary is computed by both clusters from
+// identical inputs, the one holding its from node stores it), its new flow,
+// mean phase and half phase difference are staged in LDS, and the node
+// averages are then summed from LDS in the node's CSR order (no atomics).
+// The running sums over contingencies for the step-2 means stay in the
+// registers of the thread that owns the node across the chunks.  Tiles of
+// one period follow the node order, so cut lines and far nodes read by one
+// cluster were usually just read by its neighbour on the same XCD.
+template <typename R, typename VT>
+__global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
+  constexpr int VEC = 16 / sizeof(R);
+  // contingencies per pass: 64 bytes of each row (a chunk, or half a chunk
+  // in FP64), so that the LDS footprint is the same in both precisions
+  constexpr int SUB = kChunk * 4 / int(sizeof(R)) < kChunk ? kChunk * 4 / int(sizeof(R)) : kChunk;
+  constexpr int NVMAX = SUB / VEC;  // vectors per pass row
+  using VR = Vec<R, VEC>;
+  using VV = Vec<VT, VEC>;
+  using VI = Vec<int32_t, VEC>;
+  Ctl* ctl = a.g.ctl;
+  if (ctl->done) return;
+  const Topo& tp = a.tp;
+  const int cur = ctl->cur;
+  const Buf<R, VT> A = a.st.buf[cur];
+  const Buf<R, VT> B = a.st.buf[cur ^ 1];
+  const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
+  const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
+  __shared__ __align__(16) R sW[kTileNodes * SUB];
+  __shared__ __align__(16) R sB[kTileNodes * SUB];
+  __shared__ __align__(16) R sP[kTileLines * SUB];
+  __shared__ __align__(16) R sTm[kTileLines * SUB];
+  __shared__ __align__(16) R sH[kTileLines * SUB];
+  __shared__ R sRw[kTileNodes * NVMAX], sRb[kTileNodes * NVMAX];
+  __shared__ int4 sTl[kTileLines];
+  __shared__ double sh[kBlock / kWave];
+  const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(T) * tp.Q);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t item = sweep.first; item < sweep.end; item += sweep.step) {
+    const int t = int(item / tp.Q), cq = int(item - int64_t(t) * tp.Q);
+    const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
+    const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
+    for (int j = threadIdx.x; j < nl; j += kBlock) sTl[j] = tp.tl[j0 + j];
+    R runW = R(0), runB = R(0);
+    const R* td_old = A.Td + size_t(t) * Kpp;
+    R* td_new = B.Td + size_t(t) * Kpp;
+    for (int s0 = 0; s0 < Kpp; s0 += SUB) {
+      const int c0 = s0 & ~(kChunk - 1);
+      const int w = min(kChunk, Kpp - c0);                 // chunk width
+      const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors in this pass
+      // element (item i, vector v) of this pass: base + i * w + v * VEC
+      const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
+      const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
+      lds_barrier();  // sTl written; LDS of the previous chunk no longer read
+      for (int x = threadIdx.x; x < cn * nvc; x += kBlock) {
+        const int i = x / nvc, v = x - i * nvc;
+        const size_t o = nbase + size_t(n0 + i) * w + v * VEC;
+        *reinterpret_cast<VR*>(sW + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.W + o);
+        *reinterpret_cast<VR*>(sB + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.TB + o);
+      }
+      lds_barrier();
+      for (int x = threadIdx.x; x < nl * nvc; x += kBlock) {
+        const int j = x / nvc, v = x - j * nvc;
+        const int4 e = sTl[j];
+        const int l = e.x;
+        const int k0 = s0 + v * VEC;
+        const size_t ol = lbase + size_t(l) * w + v * VEC;
+        const VR P = *reinterpret_cast<const VR*>(A.P + ol);
+        const VR Tm = *reinterpret_cast<const VR*>(A.Tm + ol);
+        const VV V1 = *reinterpret_cast<const VV*>(A.V1 + ol);
+        const VV V2 = *reinterpret_cast<const VV*>(A.V2 + ol);
+        const size_t ofar = nbase + size_t(e.w < 0 ? 0 : e.w) * w + v * VEC;
+        VR Wf, Wh, Bf, Bh;
+        if (e.y >= 0) {
+          Wf = *reinterpret_cast<const VR*>(sW + e.y * SUB + v * VEC);
+          Bf = *reinterpret_cast<const VR*>(sB + e.y * SUB + v * VEC);
+        } else {
+          Wf = *reinterpret_cast<const VR*>(A.W + ofar);
+          Bf = *reinterpret_cast<const VR*>(A.TB + ofar);
+        }
+        if (e.z >= 0) {
+          Wh = *reinterpret_cast<const VR*>(sW + e.z * SUB + v * VEC);
+          Bh = *reinterpret_cast<const VR*>(sB + e.z * SUB + v * VEC);
+        } else {
+          Wh = *reinterpret_cast<const VR*>(A.W + ofar);
+          Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
+        }
+        const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+        LineOut<R, VEC> o;
+        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
+                              R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+        if (e.y >= 0) {  // the cluster holding the from node stores the line
+          VR Pn, Tn;
+          VV V1n, V2n;
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            Pn.x[q] = o.p[q];
+            Tn.x[q] = o.tm[q];
+            V1n.x[q] = DIO<VT, R>::out(o.v1[q]);
+            V2n.x[q] = DIO<VT, R>::out(o.v2[q]);
+            if (ok.x[q] == l) td_new[k0 + q] = o.half[q];
+            if (check) {
+              const double dp = double(o.p[q]) - double(P.x[q]);
+              acc[4] += 2.0 * dp * dp;
+            }
+          }
+          st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
+          st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
+          st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
+          st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+        }
+        VR Po, To, Ho;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          Po.x[q] = o.p[q];
+          To.x[q] = o.tm[q];
+          Ho.x[q] = o.half[q];
+        }
+        *reinterpret_cast<VR*>(sP + j * SUB + v * VEC) = Po;
+        *reinterpret_cast<VR*>(sTm + j * SUB + v * VEC) = To;
+        *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
+      }
+      lds_barrier();
+      for (int x = threadIdx.x; x < cn * nvc; x += kBlock) {
+        const int i = x / nvc, v = x - i * nvc, n = n0 + i;
+        const int k0 = s0 + v * VEC;
+        R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
+        bool first = true;
+        for (int qq = tp.node_lptr[n]; qq < tp.node_lptr[n + 1]; ++qq) {
+          const int ent = tp.tcsr[qq];
+          const int j = ent >> 1;
+          const bool to_end = ent & 1;
+          const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + v * VEC);
+          const VR To = *reinterpret_cast<const VR*>(sTm + j * SUB + v * VEC);
+          const VR Ho = *reinterpret_cast<const VR*>(sH + j * SUB + v * VEC);
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            const R pj = to_end ? Po.x[q] : -Po.x[q];
+            const R thj = to_end ? To.x[q] - Ho.x[q] : To.x[q] + Ho.x[q];
+            sp[q] += pj;
+            sb[q] += thj;
+            if (first) c[q] = thj;
+            const R d = thj - c[q];
+            s1[q] += d;
+            s2[q] += d * d;
+          }
+          first = false;
+        }
+        for (int qq = tp.node_nptr[n]; qq < tp.node_nptr[n + 1]; ++qq) {
+          const int jd = tp.node_nterm[qq];
+          const R pj = a.st.pnc[size_t(jd) * T + t];
+          const R thj = a.st.thnc[size_t(jd) * T + t];
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            sp[q] += pj;
+            sb[q] += thj;
+            if (first) c[q] = thj;
+            const R d = thj - c[q];
+            s1[q] += d;
+            s2[q] += d * d;
+          }
+          first = false;
+        }
+        const size_t on = nbase + size_t(n) * w + v * VEC;
+        const VR Uo = ld_stream(reinterpret_cast<const VR*>(A.U + on));
+        const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
+        const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
+        const double dg = tp.deg[n];
+        const R rdg = R(dg);
+        VR Un, Wn, Bn;
+        R sumw = R(0), sumb = R(0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const bool valid = k0 + q < tp.Kp;
+          const R pb = sp[q] / rdg;
+          const R tb = sb[q] / rdg;
+          const R un = Uo.x[q] + pb;
+          const R wn = un + pb;
+          if (check && valid) {
+            const double dpb = double(pb);
+            acc[0] += dg * dpb * dpb;
+            acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) / dg, 0.0);
+            const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
+            acc[2] += dg * dd * dd;
+            const double dt = double(tb) - double(Bo.x[q]);
+            acc[3] += dg * dt * dt;
+          }
+          Un.x[q] = valid ? un : R(0);
+          Wn.x[q] = valid ? wn : R(0);
+          Bn.x[q] = valid ? tb : R(0);
+          sumw += Wn.x[q];
+          sumb += Bn.x[q];
+        }
+        st_stream(reinterpret_cast<VR*>(B.U + on), Un);
+        st_stream(reinterpret_cast<VR*>(B.W + on), Wn);
+        st_stream(reinterpret_cast<VR*>(B.TB + on), Bn);
+        sRw[x] = sumw;
+        sRb[x] = sumb;
+      }
+      lds_barrier();
+      if (threadIdx.x < cn) {
+        for (int v = 0; v < nvc; ++v) {
+          runW += sRw[threadIdx.x * nvc + v];
+          runB += sRb[threadIdx.x * nvc + v];
+        }
+      }
+    }
+    if (threadIdx.x < cn) {
+      const size_t o = size_t(n0 + threadIdx.x) * T + t;
+      a.st.avgW[o] = runW / R(tp.Kp);
+      a.st.avgTB[o] = runB / R(tp.Kp);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double s = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) a.g.part_sweep[5 * blockIdx.x + k] = s;
+  }
+}
+
 // Step 2 for all generators, loads and batteries, one per wavefront.
 template <typename R, typename VT, int E>
 __global__ void __launch_bounds__(kBlock) k_devices(KArgs<R, VT> a) {
@@ -389,7 +614,7 @@ __device__ void finalize_body(const KArgs<R, VT>& a, int n_sweep, int n_nc) {
 
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_finalize(KArgs<R, VT> a) {
-  finalize_body(a, a.g.n_sweep_blocks, a.g.n_nc_blocks);
+  finalize_body(a, a.g.n_part, a.g.n_nc_blocks);
 }
 
 // u <- su u after a penalty change for one (period, node) row of the current
@@ -404,7 +629,8 @@ __device__ inline void rescale_row(const KArgs<R, VT>& a, const Buf<R, VT>& C, R
   R sumw = R(0);
   if (act) {
     for (int v = q; v < a.g.nv; v += lpr) {
-      const size_t off = size_t(row) * a.tp.Kpp + v * VEC;
+      const int t = int(row / a.tp.N), n = int(row - int64_t(t) * a.tp.N);
+      const size_t off = ck_off(t, n, v * VEC, a.tp.N, a.tp.Kpp);
       const VR U = *reinterpret_cast<const VR*>(C.U + off);
       const VR W = *reinterpret_cast<const VR*>(C.W + off);
       VR Un, Wn;
@@ -573,7 +799,7 @@ __global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, do
     const int t = int(i % T);
     const int l = int((i / T) % tp.L);
     const int k = int(i / (int64_t(T) * tp.L));
-    const size_t o = (size_t(t) * tp.L + l) * tp.Kpp + k;
+    const size_t o = ck_off(t, l, k, tp.L, tp.Kpp);
     const double P = double(C.P[o]);
     if (field == 0) {
       dst[i] = P;
@@ -586,7 +812,7 @@ __global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, do
     if (field == 2) dst[i] = th2;
     if (field == 3 || field == 4) {
       const int nd = field == 3 ? tp.line_from[l] : tp.line_to[l];
-      const double tb = double(C.TB[(size_t(t) * tp.N + nd) * tp.Kpp + k]);
+      const double tb = double(C.TB[ck_off(t, nd, k, tp.N, tp.Kpp)]);
       const double vs = double(DIO<VT, R>::in(field == 3 ? C.V1[o] : C.V2[o]));
       dst[i] = sv * (vs + (field == 3 ? th1 : th2) - tb);
     }
@@ -596,7 +822,7 @@ __global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, do
     const int t = int(i % T);
     const int n = int((i / T) % tp.N);
     const int k = int(i / (int64_t(T) * tp.N));
-    const size_t o = (size_t(t) * tp.N + n) * tp.Kpp + k;
+    const size_t o = ck_off(t, n, k, tp.N, tp.Kpp);
     if (field == 5) dst[i] = double(C.U[o]);
     if (field == 6) dst[i] = double(C.W[o]) - double(C.U[o]);
     if (field == 7) dst[i] = double(C.TB[o]);
@@ -649,7 +875,22 @@ int sweep_resident_blocks() {
 
 template <typename R, typename VT>
 void launch_sweep(const KArgs<R, VT>& a, hipStream_t s) {
-  k_sweep<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+  if (a.g.tile_blocks > 0)
+    k_sweep_tile<R, VT><<<a.g.tile_blocks, kBlock, 0, s>>>(a);
+  else
+    k_sweep<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+}
+
+// Blocks of the tiled sweep resident at once on the current device.
+template <typename R, typename VT>
+int tile_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile<R, VT>, kBlock, 0) !=
+      hipSuccess)
+    return 0;
+  return cus * per;
 }
 
 template <typename R, typename VT>
@@ -755,6 +996,7 @@ int sweep_batch_resident_blocks() {
   template void launch_batch_iter_rescale<R, VT>(const BatchTab&, hipStream_t);      \
   template int sweep_batch_resident_blocks<R, VT>();                                 \
   template int sweep_resident_blocks<R, VT>();                                       \
+  template int tile_resident_blocks<R, VT>();                                        \
   template void launch_devices<R, VT>(const KArgs<R, VT>&, hipStream_t);            \
   template void launch_sweep<R, VT>(const KArgs<R, VT>&, hipStream_t);              \
   template void launch_finalize<R, VT>(const KArgs<R, VT>&, hipStream_t);           \
