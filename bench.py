@@ -204,7 +204,8 @@ def summarize_stats(directory, out_path, command):
     print("\n".join(lines))
 
 
-def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_write):
+def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_write,
+                      request_dir=None, command_request=None):
     """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
     dispatch), each scaled by what the counter reads for a plain 1 GiB -> 1 GiB
     elementwise copy in the same run."""
@@ -224,7 +225,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_wri
     wr, wcopy, wsweep, nw = per_kernel(write_dir, "WRITE_SIZE")
     read_b = fsweep * 1024 * fr
     write_b = wsweep * 1024 * wr
-    d = {"kernel": "k_sweep_tile", "workload": "large, FP32 iterate",
+    d = {"kernel": "k_sweep_tile", "workload": "large (N=10000 L=13000 T=96 K=200), FP32 iterate",
          "kernel_source_hash": kernel_source_hash(),
          "fetch_kib_per_launch_raw": fsweep, "write_kib_per_launch_raw": wsweep,
          "copy_fetch_kib_raw": fcopy, "copy_write_kib_raw": wcopy,
@@ -232,6 +233,20 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_wri
          "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
          "hbm_bytes_per_launch": read_b + write_b,
          "command_fetch": command_fetch, "command_write": command_write}
+    if request_dir:
+        # read requests by size (32/64/128 bytes): exact read bytes, a check
+        # on the copy-scaled FETCH_SIZE figure
+        rows = _read_csv(_find(request_dir, "counter_collection.csv", "counter_collection_trace.csv"))
+        per = {}
+        for r in rows:
+            if "k_sweep<" in r["Kernel_Name"] or "k_sweep_tile<" in r["Kernel_Name"]:
+                per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        avg = {k: sum(v) / len(v) for k, v in per.items()}
+        d["read_requests_per_launch"] = {k.replace("TCC_EA0_", ""): v for k, v in avg.items()}
+        d["read_bytes_from_request_sizes"] = (32 * avg.get("TCC_EA0_RDREQ_32B_sum", 0.0) +
+                                              64 * avg.get("TCC_EA0_RDREQ_64B_sum", 0.0) +
+                                              128 * avg.get("TCC_EA0_RDREQ_128B_sum", 0.0))
+        d["command_request"] = command_request
     with open(out_path, "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
@@ -261,9 +276,11 @@ def main():
                          "(reference for the HBM byte counters)")
     ap.add_argument("--summarize-stats", nargs=3, metavar=("DIR", "OUT", "COMMAND"),
                     help="host only: summarise a rocprofv3 --stats run and exit")
-    ap.add_argument("--summarize-traffic", nargs=5,
-                    metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "CMD_FETCH", "CMD_WRITE"),
-                    help="host only: HBM bytes per sweep launch from two --pmc runs, then exit")
+    ap.add_argument("--summarize-traffic", nargs="+",
+                    metavar="ARG",
+                    help="host only: FETCH_DIR WRITE_DIR OUT CMD_FETCH CMD_WRITE "
+                         "[REQUEST_DIR CMD_REQUEST]: HBM bytes per sweep launch from the "
+                         "--pmc runs, then exit")
     args = ap.parse_args()
 
     if args.summarize_stats:
@@ -379,7 +396,8 @@ def main():
                    "adaptive_penalty": "every 10 iterations"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep (line prox + node aggregation + price update, fused)",
+            "kernel": "sweep: line prox + node averages + price update, fused "
+                      "(k_sweep_tile for this FP32 iterate)",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

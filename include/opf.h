@@ -71,6 +71,8 @@ typedef struct {
   double polish_factor;       /* [1.2] switch point, as a multiple of eps        */
   int32_t use_graphs;         /* 1: opf_solve replays captured graph blocks      */
   void* hip_stream;           /* hipStream_t for all work; NULL = null stream    */
+  int32_t sweep_tiles;        /* FP32 sweep over clusters of consecutive nodes:
+                                 -1 when N*T >= 65536 (default), 0 never, 1 always */
 } opf_options;
 
 /* Fills *opt with the defaults above (F64 state, eps = 1e-3 relative,
@@ -228,14 +230,16 @@ typedef struct {
   double grid_factor;    /* sweep grid as a multiple of the resident blocks     */
   double ms_per_iter;    /* measured time of one iteration with this choice     */
   int32_t from_cache;    /* 1 if read from cache_path instead of measured       */
+  int32_t tiled;         /* FP32 sweep over node clusters: 1 on, 0 off, -1 by size */
 } opf_tuning;
 
 /* Times `trials` iterations for each candidate launch configuration of the
  * loaded instance(s) (lanes per row halved/natural/doubled x sweep grid 0.5/1/2
- * times the resident blocks), keeps the fastest, and resets the iterate to
- * the zero start.  With cache_path non-NULL, a result for the same device,
- * precision and instance shape is read from that text file instead of being
- * measured, and new results are appended to it.  Synchronises. */
+ * times the resident blocks, and for one FP32 instance the tiled sweep on or
+ * off), keeps the fastest, and resets the iterate to the zero start.  With
+ * cache_path non-NULL, a result for the same device, precision and instance
+ * shape is read from that text file instead of being measured, and new
+ * results are appended to it.  Synchronises. */
 opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, opf_tuning* out);
 
 /* ---- The iterate: layout, export and import (warm start, Section 3.4) ------ */
@@ -247,9 +251,9 @@ opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, op
  * iteration's update) are [T][chunk][L][w] and node arrays U (scaled price),
  * W (= pbar + U) and TB (thetabar) are [T][chunk][N][w]: the K+1
  * contingencies, padded to Kpp (a multiple of 4), are split into chunks of
- * 16, chunk c holding contingencies 16c .. 16c + w - 1 with
- * w = min(16, Kpp - 16c), so element (t, i, k) is at
- * (t * Kpp + 16 c) * count + i * w + (k - 16 c), c = k / 16.  Td ([T][Kpp])
+ * `chunk` (32), chunk c holding contingencies c*chunk .. c*chunk + w - 1 with
+ * w = min(chunk, Kpp - c*chunk), so element (t, i, k) is at
+ * (t * Kpp + c*chunk) * count + i * w + (k - c*chunk), c = k / chunk.  Td ([T][Kpp])
  * is the half phase difference of each contingency's outaged line; device
  * arrays pnc, thnc, vbar (contingency mean of the phase duals) are
  * [G+D+B][T].  Element types: state_dtype for all but V1, V2 (dual_dtype).
@@ -257,6 +261,7 @@ opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, op
 typedef struct {
   int32_t N, T, K, Kpp, L, Jnc;
   int32_t state_dtype, dual_dtype;
+  int32_t chunk;          /* contingencies per chunk */
   size_t P, Tm, V1, V2, Td, U, W, TB, pnc, thnc, vbar;
 } opf_layout;
 opf_status opf_state_layout(opf_ctx* ctx, int32_t instance, opf_layout* out);

@@ -41,6 +41,7 @@ class Options(Structure):
         ("inner_iters", c_int32), ("inner_omega_scale", c_double),
         ("polish_fp64", c_int32), ("polish_factor", c_double), ("use_graphs", c_int32),
         ("hip_stream", c_void_p),
+        ("sweep_tiles", c_int32),
     ]
 
 
@@ -78,13 +79,13 @@ class Resid(Structure):
 
 class Tuning(Structure):
     _fields_ = [("lanes_shift", c_int32), ("grid_factor", c_double),
-                ("ms_per_iter", c_double), ("from_cache", c_int32)]
+                ("ms_per_iter", c_double), ("from_cache", c_int32), ("tiled", c_int32)]
 
 
 class Layout(Structure):
     _fields_ = [("N", c_int32), ("T", c_int32), ("K", c_int32), ("Kpp", c_int32),
                 ("L", c_int32), ("Jnc", c_int32), ("state_dtype", c_int32),
-                ("dual_dtype", c_int32),
+                ("dual_dtype", c_int32), ("chunk", c_int32),
                 *[(n, c_size_t) for n in ["P", "Tm", "V1", "V2", "Td", "U", "W", "TB", "pnc",
                                           "thnc", "vbar"]]]
 
@@ -307,7 +308,8 @@ class Solver:
     def view(self, name: str, instance: int = 0):
         """Zero-copy views of one array of the current iterate, valid until
         the next iteration.  Line and node arrays: a list with one [T, count,
-        w] tensor per chunk of (at most 16) contingencies; Td [T, Kpp];
+        w] tensor per chunk of contingencies (layout()['chunk'] wide, the last one
+        narrower); Td [T, Kpp];
         device arrays [Jnc, T]."""
         torch = self.torch
         lay = self.layout(instance)
@@ -324,8 +326,9 @@ class Solver:
         count = L if name in ("P", "Tm", "V1", "V2") else N
         flat = self.ws.view(dtype) if self.ws.numel() % esize == 0 else None
         out = []
-        for c0 in range(0, Kpp, 16):
-            w = min(16, Kpp - c0)
+        ch = lay["chunk"]
+        for c0 in range(0, Kpp, ch):
+            w = min(ch, Kpp - c0)
             out.append(flat.as_strided((T, count, w), (Kpp * count, w, 1), off + c0 * count))
         return out
 

@@ -144,7 +144,8 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Deterministic block sum; the result is valid in thread 0.
+// Deterministic block sum over NT threads; the result is valid in thread 0.
+template <int NT = kBlock>
 __device__ inline double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -152,7 +153,7 @@ __device__ inline double block_sum(double v, double* sh) {
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / kWave; ++i) r += sh[i];
+    for (int i = 0; i < NT / kWave; ++i) r += sh[i];
   __syncthreads();
   return r;
 }

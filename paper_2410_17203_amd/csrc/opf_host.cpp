@@ -136,6 +136,7 @@ struct opf_ctx {
   // launch tuning
   int lanes_shift = 0;       // lanes per row = natural value << shift (or >>)
   double grid_factor = 1.0;  // sweep grid = resident blocks * factor
+  int tile_mode = -1;        // tiled FP32 sweep: -1 by size, 0 off, 1 on
   // pinned readback buffers
   Ctl* h_ctl = nullptr;
   int h_ctl_count = 0;
@@ -291,7 +292,9 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resid
   // the tiled sweep is used for the FP32 iterate; in FP64 the node-row sweep
   // measured faster on MI355X (its rows are twice as wide, so each holds more
   // outstanding loads, and the tile's half-chunk passes re-read lines)
-  if (!c->batch && vec == 4 && s.topo.Q > 0 && resident_tile >= 8) {
+  // by default only on instances large enough to fill the chip with tiles
+  const bool want_tiles = c->tile_mode < 0 ? int64_t(s.N) * s.T >= 65536 : c->tile_mode == 1;
+  if (!c->batch && vec == 4 && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
     const int64_t items = int64_t(s.T) * s.topo.Q;
     const int cap = std::min(kMaxSweepBlocks,
                              std::max(8, int(resident_tile * c->grid_factor) / 8 * 8));
@@ -1316,6 +1319,7 @@ void opf_default_options(opf_options* o) {
   o->polish_factor = 1.2;
   o->use_graphs = 1;
   o->hip_stream = nullptr;
+  o->sweep_tiles = -1;
 }
 
 opf_status opf_create(const opf_options* opt, opf_ctx** out) {
@@ -1339,12 +1343,15 @@ opf_status opf_create(const opf_options* opt, opf_ctx** out) {
   if (o.max_iter < 0 || o.min_iter < 0 || o.block_iters < 1)
     return fail(nullptr, OPF_E_INVALID, "need max_iter >= 0, min_iter >= 0, block_iters >= 1");
   if (!(o.polish_factor >= 1.0)) return fail(nullptr, OPF_E_INVALID, "polish_factor must be >= 1");
+  if (o.sweep_tiles < -1 || o.sweep_tiles > 1)
+    return fail(nullptr, OPF_E_INVALID, "sweep_tiles must be -1, 0 or 1");
   if (o.inner_iters < 1 || !(o.inner_omega_scale > 0))
     return fail(nullptr, OPF_E_INVALID, "need inner_iters >= 1 and inner_omega_scale > 0");
   opf_ctx* c = new opf_ctx();
   c->opt = o;
   c->stream = reinterpret_cast<hipStream_t>(o.hip_stream);
   c->bf16_duals = o.dual_dtype == OPF_BF16;
+  c->tile_mode = o.sweep_tiles;
   *out = c;
   return OPF_OK;
 }
@@ -1612,10 +1619,12 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     std::string k;
     int shift;
     double gf, ms;
-    while (in >> k >> shift >> gf >> ms)
+    int tiled;
+    while (in >> k >> shift >> gf >> tiled >> ms)
       if (k == key.str()) {
         best.lanes_shift = shift;
         best.grid_factor = gf;
+        best.tiled = tiled;
         best.ms_per_iter = ms;
         cached = true;
       }
@@ -1626,8 +1635,12 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
+    const bool tiles_possible = !c->batch && c->has32 && c->inst[0].topo.Q > 0;
+    for (int tm = 0; tm <= (tiles_possible ? 1 : 0); ++tm)
     for (int shift = -1; shift <= 1; ++shift) {
       for (double gf : {0.5, 1.0, 2.0}) {
+        if (tm == 1 && shift != 0) continue;  // the tiled sweep has no lane groups
+        c->tile_mode = tiles_possible ? tm : -1;
         c->lanes_shift = shift;
         c->grid_factor = gf;
         opf_status s = refresh_geometry(c);
@@ -1648,6 +1661,7 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
           best.ms_per_iter = per;
           best.lanes_shift = shift;
           best.grid_factor = gf;
+          best.tiled = c->tile_mode;
         }
       }
     }
@@ -1657,11 +1671,12 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);
       outf << key.str() << " " << best.lanes_shift << " " << best.grid_factor << " "
-           << best.ms_per_iter << "\n";
+           << best.tiled << " " << best.ms_per_iter << "\n";
     }
   }
   c->lanes_shift = best.lanes_shift;
   c->grid_factor = best.grid_factor;
+  c->tile_mode = best.tiled;
   opf_status s = refresh_geometry(c);
   if (s != OPF_OK) return s;
   s = reset_state(c);
@@ -1688,6 +1703,7 @@ opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
   out->Jnc = x.Jnc;
   out->state_dtype = c->precision == 0 ? OPF_F64 : OPF_F32;
   out->dual_dtype = c->precision == 0 ? OPF_F64 : (c->bf16_duals ? OPF_BF16 : OPF_F32);
+  out->chunk = kChunk;
   auto off = [&](const void* p) { return size_t(static_cast<const char*>(p) - c->ws); };
   auto fill = [&](const auto& st) {
     const auto& b = st.buf[cur];

@@ -7,8 +7,9 @@
 //   device arrays [Jnc][T]          generator/load/battery power, phase and
 //                                   the contingency-averaged phase dual
 // The K+1 contingencies (padded to Kpp, a multiple of 4) are split into
-// chunks of 16 (the last one w = Kpp - 16 c wide).  Within a chunk the w
-// contingencies of one line or node are contiguous (64 bytes in FP32) and
+// chunks of 32 (the last one w = Kpp - 32 c wide).  Within a chunk the w
+// contingencies of one line or node are contiguous (128 bytes in FP32, one
+// L2 line, so an isolated gather wastes nothing) and
 // consecutive lines or nodes follow each other, so a tile of neighbouring
 // nodes (or the lines they own) in one period and chunk is one contiguous
 // run of memory, and every 16-byte vector of contingencies lies in one chunk.
@@ -30,7 +31,10 @@ constexpr int kBlock = 256;      // threads per block of every kernel
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kRing = 4096;      // residual records kept on the device
 constexpr int kMaxAdjInner = 32; // inner iterations the adjoint's clip recorder holds
-constexpr int kChunk = 16;       // contingencies per chunk of the line and node arrays
+#ifndef OPF_CHUNK
+#define OPF_CHUNK 32
+#endif
+constexpr int kChunk = OPF_CHUNK; // contingencies per chunk of the line and node arrays
 #ifndef OPF_TILE_NODES
 #define OPF_TILE_NODES 64
 #endif
@@ -39,6 +43,10 @@ constexpr int kChunk = 16;       // contingencies per chunk of the line and node
 #endif
 constexpr int kTileNodes = OPF_TILE_NODES;  // most nodes in one cluster of the tiled sweep
 constexpr int kTileLines = OPF_TILE_LINES;  // most lines touching one cluster
+#ifndef OPF_TILE_BLOCK
+#define OPF_TILE_BLOCK 512
+#endif
+constexpr int kTileBlock = OPF_TILE_BLOCK;  // threads per workgroup of the tiled sweep
 
 // Element index of contingency k of item i (a line, count = L, or a node,
 // count = N) in period t.

@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 
 // ---------------------------------------------------------------------------
 // Tiled sweep: steps 1 and 3 for one (period, cluster of consecutive nodes)
-// per workgroup, chunk by chunk of 16 contingencies.  The cluster's old W
+// per workgroup, chunk by chunk of 32 contingencies.  The cluster's old W
 // and thetabar rows are staged in LDS; every line touching the cluster is
 // proxed once per cluster (a line with both ends inside is read and computed
 // once; a line cut by the cluster boundary is computed by both clusters from
@@ -300,11 +300,14 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
 template <typename R, typename VT>
-__global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
+__global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
   constexpr int VEC = 16 / sizeof(R);
-  // contingencies per pass: 64 bytes of each row (a chunk, or half a chunk
-  // in FP64), so that the LDS footprint is the same in both precisions
-  constexpr int SUB = kChunk * 4 / int(sizeof(R)) < kChunk ? kChunk * 4 / int(sizeof(R)) : kChunk;
+  // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
+  // chunk in FP64), so that the LDS footprint is the same in both precisions
+#ifndef OPF_PASS_BYTES
+#define OPF_PASS_BYTES 128
+#endif
+  constexpr int SUB = OPF_PASS_BYTES / int(sizeof(R)) < kChunk ? OPF_PASS_BYTES / int(sizeof(R)) : kChunk;
   constexpr int NVMAX = SUB / VEC;  // vectors per pass row
   using VR = Vec<R, VEC>;
   using VV = Vec<VT, VEC>;
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
   __shared__ __align__(16) R sH[kTileLines * SUB];
   __shared__ R sRw[kTileNodes * NVMAX], sRb[kTileNodes * NVMAX];
   __shared__ int4 sTl[kTileLines];
-  __shared__ double sh[kBlock / kWave];
+  __shared__ double sh[kTileBlock / kWave];
   const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(T) * tp.Q);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -332,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
     const int t = int(item / tp.Q), cq = int(item - int64_t(t) * tp.Q);
     const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
     const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
-    for (int j = threadIdx.x; j < nl; j += kBlock) sTl[j] = tp.tl[j0 + j];
+    for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
     R runW = R(0), runB = R(0);
     const R* td_old = A.Td + size_t(t) * Kpp;
     R* td_new = B.Td + size_t(t) * Kpp;
@@ -344,14 +347,14 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
       const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
       const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
       lds_barrier();  // sTl written; LDS of the previous chunk no longer read
-      for (int x = threadIdx.x; x < cn * nvc; x += kBlock) {
+      for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
         const int i = x / nvc, v = x - i * nvc;
         const size_t o = nbase + size_t(n0 + i) * w + v * VEC;
         *reinterpret_cast<VR*>(sW + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.W + o);
         *reinterpret_cast<VR*>(sB + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.TB + o);
       }
       lds_barrier();
-      for (int x = threadIdx.x; x < nl * nvc; x += kBlock) {
+      for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
         const int j = x / nvc, v = x - j * nvc;
         const int4 e = sTl[j];
         const int l = e.x;
@@ -413,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
         *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
       }
       lds_barrier();
-      for (int x = threadIdx.x; x < cn * nvc; x += kBlock) {
+      for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
         const int i = x / nvc, v = x - i * nvc, n = n0 + i;
         const int k0 = s0 + v * VEC;
         R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
@@ -507,7 +510,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tile(KArgs<R, VT> a) {
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double s = block_sum(acc[k], sh);
+    const double s = block_sum<kTileBlock>(acc[k], sh);
     if (threadIdx.x == 0) a.g.part_sweep[5 * blockIdx.x + k] = s;
   }
 }
@@ -876,7 +879,7 @@ int sweep_resident_blocks() {
 template <typename R, typename VT>
 void launch_sweep(const KArgs<R, VT>& a, hipStream_t s) {
   if (a.g.tile_blocks > 0)
-    k_sweep_tile<R, VT><<<a.g.tile_blocks, kBlock, 0, s>>>(a);
+    k_sweep_tile<R, VT><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
   else
     k_sweep<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
 }
@@ -887,7 +890,7 @@ int tile_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile<R, VT>, kBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile<R, VT>, kTileBlock, 0) !=
       hipSuccess)
     return 0;
   return cus * per;

@@ -29,6 +29,7 @@ def test_default_options_follow_the_paper(lib):
     assert (o.rho_p, o.rho_theta, o.mu, o.gamma, o.adapt_every) == (1.0, 1.0, 2.0, 1.1, 10)
     assert o.inner_iters == 10 and o.check_every == 1 and o.block_iters == 50
     assert o.polish_fp64 == 1 and o.polish_factor == 1.2
+    assert o.sweep_tiles == -1
 
 
 def _ctx(lib, **kw):
@@ -53,6 +54,7 @@ def test_option_validation(lib):
     assert _ctx(lib, state_dtype=binding.F64, dual_dtype=binding.BF16)[0] == -1
     assert _ctx(lib, inner_iters=0)[0] == -1
     assert _ctx(lib, polish_factor=0.5)[0] == -1
+    assert _ctx(lib, sweep_tiles=2)[0] == -1
     st, ctx = _ctx(lib, state_dtype=binding.F32, dual_dtype=binding.BF16)
     assert st == 0
     lib.opf_destroy(ctx)

@@ -44,6 +44,15 @@ def make(name):
         inst.line_cap[4] = 0.0        # a live line that can carry no power
         inst.gen_ramp[0] = 0.0        # a generator without ramp limit
         return inst
+    if name == "hub":  # a node with more lines than one sweep tile holds
+        inst = synth.make_instance("hub", N=150, L=210, G=20, D=100, B=4, T=3, K=3, seed=150)
+        extra = np.arange(1, 141)
+        src = np.arange(140) % len(inst.line_from)
+        inst.line_from = np.r_[inst.line_from, np.zeros(140, int)].astype(np.int32)
+        inst.line_to = np.r_[inst.line_to, extra].astype(np.int32)
+        inst.line_sus = np.r_[inst.line_sus, np.asarray(inst.line_sus)[src]]
+        inst.line_cap = np.r_[inst.line_cap, np.asarray(inst.line_cap)[src]]
+        return inst
     if name == "no_batteries_T1":
         return synth.make_instance("nb", N=25, L=35, G=5, D=18, B=0, T=1, K=9, seed=25)
     raise KeyError(name)
@@ -106,11 +115,15 @@ def test_fp64_iterates_match_oracle(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["medium", "wide_T"])
-def test_fp32_iterates_match_oracle(name):
-    say(f"[parity fp32] {name}")
+@pytest.mark.parametrize("tiles", [0, 1])
+@pytest.mark.parametrize("name", ["medium", "wide_T", "edge", "no_batteries_T1", "hub"])
+def test_fp32_iterates_match_oracle(name, tiles):
+    """FP32 iterate with the node-row sweep and with the sweep over clusters
+    of consecutive nodes (several chunks of contingencies, a ragged last
+    chunk, outaged and zero-capacity lines, T = 1)."""
+    say(f"[parity fp32] {name} tiles={tiles}")
     ref, hist = oracle_run(name, 200, 0)
-    s = gpu_run(name, 200, "f32", 0, polish_fp64=0)
+    s = gpu_run(name, 200, "f32", 0, polish_fp64=0, sweep_tiles=tiles)
     compare_fields(s, ref, 1e-4)
     r = s.residuals()
     b = hist[-1]
@@ -163,10 +176,11 @@ def test_fp32_solve_with_fp64_polish_reaches_tolerance():
     s.close()
 
 
-def test_repeat_runs_are_bitwise_identical():
-    say("[determinism] medium f32")
-    a = gpu_run("medium", 30, "f32", 10, polish_fp64=0)
-    b = gpu_run("medium", 30, "f32", 10, polish_fp64=0)
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_repeat_runs_are_bitwise_identical(tiles):
+    say(f"[determinism] medium f32 tiles={tiles}")
+    a = gpu_run("medium", 30, "f32", 10, polish_fp64=0, sweep_tiles=tiles)
+    b = gpu_run("medium", 30, "f32", 10, polish_fp64=0, sweep_tiles=tiles)
     for f in ["P", "TH1", "V2", "U", "THBAR", "PNC"]:
         assert torch.equal(a.field(f), b.field(f)), f
     assert a.history() == b.history()
@@ -174,10 +188,11 @@ def test_repeat_runs_are_bitwise_identical():
     b.close()
 
 
-def test_bf16_duals_run_and_stay_close():
-    say("[bf16 duals] medium")
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_bf16_duals_run_and_stay_close(tiles):
+    say(f"[bf16 duals] medium tiles={tiles}")
     ref, hist = oracle_run("medium", 200, 0)
-    s = gpu_run("medium", 200, "f32", 0, dual_dtype="bf16", polish_fp64=0)
+    s = gpu_run("medium", 200, "f32", 0, dual_dtype="bf16", polish_fp64=0, sweep_tiles=tiles)
     r = s.residuals()
     assert math.isfinite(r["rms_primal"]) and math.isfinite(r["rms_dual"])
     # no parity target for BF16 storage: report the error against the oracle

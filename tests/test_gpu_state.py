@@ -17,7 +17,7 @@ def say(msg):
 
 
 def small(seed=21, **kw):
-    args = dict(N=40, L=56, G=8, D=30, B=3, T=12, K=21, seed=seed)  # two chunks
+    args = dict(N=40, L=56, G=8, D=30, B=3, T=12, K=37, seed=seed)  # two chunks
     args.update(kw)
     return synth.make_instance("state", **args)
 
