@@ -100,7 +100,10 @@ typedef struct {
   const int32_t* outage;                  /* K entries, distinct or -1       */
   int32_t G;
   const int32_t* gen_node;
-  const double *gen_c2, *gen_c1;          /* c2 > 0                          */
+  const double *gen_c2, *gen_c1;          /* c2 >= 0; c2 = 0 is a linear cost, and
+                                             pmin < pmax <= 0 with c1 = the
+                                             curtailment cost is a curtailable
+                                             load (Section 2.1)               */
   const double *gen_pmin, *gen_pmax;      /* G*T, pmin <= pmax               */
   const double* gen_ramp;                 /* G                               */
   int32_t D;

@@ -220,8 +220,8 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
   for (int g = 0; g < n->G; ++g) {
     if (!node_ok(n->gen_node[g])) return fail(c, OPF_E_INVALID, "generator node out of range");
     deg[n->gen_node[g]]++;
-    if (!(n->gen_c2[g] > 0.0) || !finite(n->gen_c2[g]) || !finite(n->gen_c1[g]))
-      return fail(c, OPF_E_INVALID, "generator costs must be finite with c2 > 0");
+    if (!(n->gen_c2[g] >= 0.0) || !finite(n->gen_c2[g]) || !finite(n->gen_c1[g]))
+      return fail(c, OPF_E_INVALID, "generator costs must be finite with c2 >= 0");
     if (std::isnan(n->gen_ramp[g])) return fail(c, OPF_E_INVALID, "generator ramp is NaN");
     for (int t = 0; t < T; ++t) {
       const double lo = n->gen_pmin[size_t(g) * T + t], hi = n->gen_pmax[size_t(g) * T + t];

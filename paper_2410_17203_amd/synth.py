@@ -393,3 +393,24 @@ def two_node(d: float = 1.0, c2=(0.5, 0.25), c1=(1.0, 2.0), pmax=(5.0, 5.0),
         bat_node=np.zeros(0, np.int32), bat_P=f([]), bat_dur=f([]), bat_eta=f([]),
         bat_alpha=f([]), meta={},
     )
+
+
+def with_curtailable_loads(inst: Instance, cost: float = 500.0) -> Instance:
+    """The same network with every fixed load replaced by a curtailable one
+    (Section 2.1: a generator with pmin = -d_t < pmax = 0 and linear cost;
+    serving the demand in full is worth `cost` per unit).  Loads become the
+    last generators; the instance has no fixed loads."""
+    import dataclasses as _dc
+    G, D, T = len(inst.gen_node), len(inst.load_node), int(inst.T)
+    d = np.asarray(inst.load_d, float).reshape(D, T)
+    return _dc.replace(
+        inst,
+        gen_node=np.r_[inst.gen_node, inst.load_node].astype(np.int32),
+        gen_c2=np.r_[inst.gen_c2, np.zeros(D)],
+        gen_c1=np.r_[inst.gen_c1, np.full(D, cost)],
+        gen_pmin=np.r_[np.asarray(inst.gen_pmin, float).reshape(G, T), -d],
+        gen_pmax=np.r_[np.asarray(inst.gen_pmax, float).reshape(G, T), np.zeros((D, T))],
+        gen_ramp=np.r_[inst.gen_ramp, np.full(D, np.inf)],
+        load_node=np.zeros(0, np.int32),
+        load_d=np.zeros((0, T)),
+    )

@@ -75,7 +75,7 @@ def test_workspace_size_scales_with_contingencies(lib):
     (lambda i: i.line_sus.__setitem__(0, 0.0), "susceptance"),
     (lambda i: i.line_cap.__setitem__(1, -1.0), "capacity"),
     (lambda i: i.line_from.__setitem__(2, 99), "out of range"),
-    (lambda i: i.gen_c2.__setitem__(0, 0.0), "c2 > 0"),
+    (lambda i: i.gen_c2.__setitem__(0, -1e-3), "c2 >= 0"),
     (lambda i: i.gen_pmax.__setitem__((0, 0), -5.0), "pmin <= pmax"),
     (lambda i: i.load_d.__setitem__((0, 0), np.nan), "load demand"),
     (lambda i: i.bat_eta.__setitem__(0, 1.5), "eta"),

@@ -53,6 +53,10 @@ def make(name):
         inst.line_sus = np.r_[inst.line_sus, np.asarray(inst.line_sus)[src]]
         inst.line_cap = np.r_[inst.line_cap, np.asarray(inst.line_cap)[src]]
         return inst
+    if name == "curtailable":  # loads as linear-cost generators (Section 2.1)
+        base = synth.make_instance("curt", N=30, L=45, G=6, D=20, B=2, T=6, K=4, seed=41)
+        base.gen_pmax = np.asarray(base.gen_pmax) * 0.5  # some demand goes unserved
+        return synth.with_curtailable_loads(base, cost=50.0)
     if name == "no_batteries_T1":
         return synth.make_instance("nb", N=25, L=35, G=5, D=18, B=0, T=1, K=9, seed=25)
     raise KeyError(name)
@@ -96,7 +100,8 @@ def compare_fields(s, ref, tol, skip=()):
     return worst
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1"])
+@pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1",
+                                  "curtailable"])
 def test_fp64_iterates_match_oracle(name):
     say(f"[parity fp64] {name}")
     ref, hist = oracle_run(name, 200, 0)
@@ -116,7 +121,8 @@ def test_fp64_iterates_match_oracle(name):
 
 
 @pytest.mark.parametrize("tiles", [0, 1])
-@pytest.mark.parametrize("name", ["medium", "wide_T", "edge", "no_batteries_T1", "hub"])
+@pytest.mark.parametrize("name", ["medium", "wide_T", "edge", "no_batteries_T1", "hub",
+                                  "curtailable"])
 def test_fp32_iterates_match_oracle(name, tiles):
     """FP32 iterate with the node-row sweep and with the sweep over clusters
     of consecutive nodes (several chunks of contingencies, a ragged last

@@ -246,3 +246,20 @@ def test_solution_independent_of_initial_penalty(tiny_converged):
     assert rb.converged
     np.testing.assert_allclose(b.dispatch().numpy(), s.dispatch().numpy(), atol=2e-5)
     np.testing.assert_allclose(b.lmp().numpy(), s.lmp().numpy(), rtol=1e-4)
+
+
+def test_curtailable_load_sets_the_price():
+    """Section 2.1: a curtailable load is a generator with pmin = -d < pmax = 0
+    and linear cost.  With demand above the total generator capacity and an
+    uncongested line, both generators run at capacity, the load is served
+    with exactly that power, and the price at both nodes is the curtailment
+    cost (the marginal value of the unserved demand)."""
+    cost, d = 50.0, 3.0
+    base = synth.two_node(d=d, c2=(0.5, 0.25), c1=(1.0, 2.0), pmax=(1.0, 0.5), cap=10.0)
+    inst = synth.with_curtailable_loads(base, cost=cost)
+    s = Solver(inst, Options(eps=1e-9, eps_relative=False, max_iter=400000))
+    r = s.solve()
+    assert r.converged
+    p = s.dispatch()[:, 0].numpy()
+    np.testing.assert_allclose(p, [1.0, 0.5, -1.5], atol=1e-6)
+    np.testing.assert_allclose(s.lmp()[:, 0].numpy(), [cost, cost], rtol=1e-5)

@@ -35,6 +35,7 @@ def test_generator_prox_bruteforce():
     x = rng.uniform(-5, 5, n)
     rho = rng.uniform(0.1, 50, n)
     c2 = rng.uniform(0.01, 0.1, n)
+    c2[: n // 3] = 0.0  # linear cost (curtailable loads, Section 2.1)
     c1 = rng.uniform(10, 50, n) * rng.choice([-1, 1], n) / 10
     pmin = rng.uniform(-2, 0.5, n)
     pmax = pmin + rng.uniform(0.0, 3, n)
