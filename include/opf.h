@@ -314,6 +314,17 @@ opf_status opf_tape_workspace_size(opf_ctx* ctx, int32_t n_iters, int32_t checkp
 opf_status opf_tape_forward(opf_ctx* ctx, int32_t n_iters, int32_t checkpoint_every,
                             void* d_tape, size_t bytes);
 
+/* As opf_tape_forward, but continuing from the current iterate (e.g. after
+ * opf_set_state: the warm-started solves of gradient-based planning, Section
+ * 5.6) and stopping by the options' rule (eps) once at least min_iters and
+ * at most max_iters iterations have run; the iterations run are the tape and
+ * their count is written to *n_run.  The iterate it starts from is a
+ * constant of the derivative.  d_tape must hold opf_tape_workspace_size(ctx,
+ * max_iters, checkpoint_every) bytes.  Synchronises. */
+opf_status opf_tape_forward_warm(opf_ctx* ctx, int32_t min_iters, int32_t max_iters,
+                                 int32_t checkpoint_every, void* d_tape, size_t bytes,
+                                 int32_t* n_run);
+
 /* Reverse pass over the recorded run.  Cotangent: d_cot_power (device,
  * [G+D+B][T] doubles, generator/load/battery order, or NULL for zero) on the
  * final device powers, plus cot_objective times the objective of the final

@@ -135,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "opf_set_state": (c_int32, [P, c_void_p, c_size_t]),
         "opf_tape_workspace_size": (c_int32, [P, c_int32, c_int32, POINTER(c_size_t)]),
         "opf_tape_forward": (c_int32, [P, c_int32, c_int32, c_void_p, c_size_t]),
+        "opf_tape_forward_warm": (c_int32, [P, c_int32, c_int32, c_int32, c_void_p, c_size_t,
+                                            POINTER(c_int32)]),
         "opf_adjoint": (c_int32, [P, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
         "opf_last_error": (c_char_p, [P]),
         "opf_destroy": (None, [P]),
@@ -361,6 +363,23 @@ class Solver:
         self._check(self.lib.opf_tape_forward(self.ctx, int(n_iters), int(checkpoint_every),
                                               c_void_p(self.tape.data_ptr()), nbytes))
         return self.residuals()
+
+    def tape_forward_warm(self, min_iters: int, max_iters: int, checkpoint_every: int = 50):
+        """Records a run from the current iterate until the stopping rule holds
+        (at least min_iters, at most max_iters iterations); returns the last
+        residual record and the number of iterations run."""
+        torch = self.torch
+        nbytes = c_size_t()
+        self._check(self.lib.opf_tape_workspace_size(self.ctx, int(max_iters),
+                                                     int(checkpoint_every), byref(nbytes)))
+        self.tape = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        n = c_int32()
+        self._check(self.lib.opf_tape_forward_warm(self.ctx, int(min_iters), int(max_iters),
+                                                   int(checkpoint_every),
+                                                   c_void_p(self.tape.data_ptr()), nbytes,
+                                                   byref(n)))
+        return self.residuals(), int(n.value)
 
     def adjoint(self, cot_power=None, cot_objective: float = 0.0) -> Dict:
         """Reverse pass of the recorded run.  cot_power: [G+D+B, T] weights on

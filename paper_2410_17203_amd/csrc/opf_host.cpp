@@ -1171,39 +1171,62 @@ opf_status tape_check(opf_ctx* c) {
   return OPF_OK;
 }
 
+// Records a forward run.  From the zero start (warm = false): exactly M
+// iterations.  From the current iterate (warm = true): the stopping rule of
+// the options after at least min_iters and at most M iterations.  The
+// iterations actually run become the tape.
 template <typename R>
-opf_status tape_forward(opf_ctx* c, int M, int C) {
+opf_status tape_forward(opf_ctx* c, int M, int C, bool warm, int min_iters, int* n_run) {
   const Inst& s = c->inst[0];
   TapePlan& t = c->tape;
-  opf_status st = reset_state(c);
-  if (st != OPF_OK) return st;
-  // run exactly M iterations: no stop on convergence or iteration limit
+  opf_status st = OPF_OK;
+  if (!warm) {
+    st = reset_state(c);
+    if (st != OPF_OK) return st;
+  }
   st = read_ctls(c);
   if (st != OPF_OK) return st;
-  c->h_ctl[0].min_iter = INT32_MAX;
-  c->h_ctl[0].max_iter = INT32_MAX;
-  HIP_TRY(c, hipMemcpyAsync(s.ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  Ctl& h0 = c->h_ctl[0];
+  const int iter0 = h0.iter, cur0 = h0.cur;
+  if (warm) {
+    h0.min_iter = iter0 + min_iters;
+    h0.max_iter = iter0 + M;
+    h0.done = 0;
+    h0.converged = 0;
+  } else {  // exactly M iterations
+    h0.min_iter = INT32_MAX;
+    h0.max_iter = INT32_MAX;
+  }
+  HIP_TRY(c, hipMemcpyAsync(s.ctl, &h0, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
   for (int i = 0; i < M; ++i) {
     HIP_TRY(c, hipMemcpyAsync(hist + i, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
-    if (i % C == 0) snapshot<R>(c, s, i & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true);
-    enqueue_n(c, 1, false, i);
+    if (i % C == 0)
+      snapshot<R>(c, s, (cur0 + i) & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true);
+    enqueue_n(c, 1, false, int64_t(iter0) + i);
   }
   HIP_TRY(c, hipMemcpyAsync(hist + M, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
-  snapshot<R>(c, s, M & 1, tape_ptr(c, t.final_snap), true);
-  HIP_TRY(c, hipGetLastError());
   c->tape_hist.assign(size_t(M) + 1, Ctl{});
   HIP_TRY(c, hipMemcpyAsync(c->tape_hist.data(), hist, sizeof(Ctl) * (size_t(M) + 1),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->host_iter = M;
-  for (int i = 0; i <= M; ++i) {
+  const int ran = c->tape_hist[M].iter - iter0;  // iterations before the stop
+  if (ran < 0 || ran > M) return fail(c, OPF_E_STATE, "forward run lost its iteration count");
+  for (int i = 0; i <= ran; ++i) {
     const Ctl& h = c->tape_hist[i];
     if (h.numeric_bad) return fail(c, OPF_E_NUMERIC, "residual became NaN or infinite");
-    if (h.iter != i || h.cur != (i & 1))
+    if (h.iter != iter0 + i || h.cur != ((cur0 + i) & 1))
       return fail(c, OPF_E_STATE, "forward run did not advance one iteration per step");
   }
+  c->tape_hist.resize(size_t(ran) + 1);
+  snapshot<R>(c, s, c->tape_hist[ran].cur, tape_ptr(c, t.final_snap), true);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  t.n_iters = ran;
+  t.n_ckpt = (size_t(ran) + C - 1) / C;
+  c->host_iter = c->tape_hist[ran].iter;
   t.ready = true;
+  if (n_run) *n_run = ran;
   return OPF_OK;
 }
 
@@ -1223,11 +1246,11 @@ opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_loa
   for (int seg = int(t.n_ckpt) - 1; seg >= 0; --seg) {
     const int i0 = seg * C, i1 = std::min(M, i0 + C);
     // recompute the segment from its checkpoint, keeping every iterate
-    snapshot<R>(c, s, i0 & 1, tape_ptr(c, t.ckpt + t.snap.total * seg), false);
+    snapshot<R>(c, s, c->tape_hist[i0].cur, tape_ptr(c, t.ckpt + t.snap.total * seg), false);
     HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + i0, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
     for (int i = i0; i < i1; ++i) {
-      snapshot<R>(c, s, i & 1, tape_ptr(c, t.seg + t.snap.total * (i - i0)), true);
-      if (i + 1 < i1) enqueue_n(c, 1, false, i);
+      snapshot<R>(c, s, c->tape_hist[i].cur, tape_ptr(c, t.seg + t.snap.total * (i - i0)), true);
+      if (i + 1 < i1) enqueue_n(c, 1, false, c->tape_hist[i].iter);
     }
     for (int i = i1 - 1; i >= i0; --i) {
       AdjArgs<R> a = adj_args<R>(c, s, tape_ptr(c, t.seg + t.snap.total * (i - i0)), ob, w_obj);
@@ -1252,11 +1275,11 @@ opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_loa
     HIP_TRY(c, hipMemcpyAsync(grad_pmax, a.gpmax, sizeof(double) * s.G * s.T,
                               hipMemcpyDeviceToDevice, c->stream));
   // leave the iterate where the forward run left it
-  snapshot<R>(c, s, M & 1, tape_ptr(c, t.final_snap), false);
+  snapshot<R>(c, s, c->tape_hist[M].cur, tape_ptr(c, t.final_snap), false);
   HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + M, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->host_iter = M;
+  c->host_iter = c->tape_hist[M].iter;
   return OPF_OK;
 }
 
@@ -1839,8 +1862,34 @@ opf_status opf_tape_forward(opf_ctx* c, int32_t n_iters, int32_t checkpoint_ever
   c->tape = plan_tape(c->inst[0], c->has32 ? 1 : 0, n_iters, checkpoint_every);
   c->tape.base = static_cast<char*>(d_tape);
   c->tape.bytes = bytes;
-  return c->tape.precision == 0 ? tape_forward<double>(c, n_iters, checkpoint_every)
-                                : tape_forward<float>(c, n_iters, checkpoint_every);
+  return c->tape.precision == 0 ? tape_forward<double>(c, n_iters, checkpoint_every, false, 0, nullptr)
+                                : tape_forward<float>(c, n_iters, checkpoint_every, false, 0, nullptr);
+}
+
+opf_status opf_tape_forward_warm(opf_ctx* c, int32_t min_iters, int32_t max_iters,
+                                 int32_t checkpoint_every, void* d_tape, size_t bytes,
+                                 int32_t* n_run) {
+  size_t need = 0;
+  opf_status s = opf_tape_workspace_size(c, max_iters, checkpoint_every, &need);
+  if (s != OPF_OK) return s;
+  if (min_iters < 0 || min_iters > max_iters)
+    return fail(c, OPF_E_INVALID, "need 0 <= min_iters <= max_iters");
+  if (!d_tape) return fail(c, OPF_E_INVALID, "tape workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_tape) % kAlign != 0)
+    return fail(c, OPF_E_INVALID, "tape workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(c, OPF_E_INVALID, "tape workspace too small: need " + std::to_string(need));
+  s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  const int active = c->h_ctl[0].precision;
+  if ((active == 0 ? 0 : 1) != (c->has32 ? 1 : 0))
+    return fail(c, OPF_E_STATE, "the current iterate is not in the configured state precision");
+  c->tape = plan_tape(c->inst[0], c->has32 ? 1 : 0, max_iters, checkpoint_every);
+  c->tape.base = static_cast<char*>(d_tape);
+  c->tape.bytes = bytes;
+  return c->tape.precision == 0
+             ? tape_forward<double>(c, max_iters, checkpoint_every, true, min_iters, n_run)
+             : tape_forward<float>(c, max_iters, checkpoint_every, true, min_iters, n_run);
 }
 
 opf_status opf_adjoint(opf_ctx* c, const double* d_cot_power, double cot_objective,
