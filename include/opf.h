@@ -71,7 +71,7 @@ typedef struct {
   double polish_factor;       /* [1.2] switch point, as a multiple of eps        */
   int32_t use_graphs;         /* 1: opf_solve replays captured graph blocks      */
   void* hip_stream;           /* hipStream_t for all work; NULL = null stream    */
-  int32_t sweep_tiles;        /* FP32 sweep over clusters of consecutive nodes:
+  int32_t sweep_tiles;        /* sweep over clusters of consecutive nodes:
                                  -1 when N*T >= 65536 (default), 0 never, 1 always */
 } opf_options;
 
@@ -238,7 +238,7 @@ typedef struct {
 
 /* Times `trials` iterations for each candidate launch configuration of the
  * loaded instance(s) (lanes per row halved/natural/doubled x sweep grid 0.5/1/2
- * times the resident blocks, and for one FP32 instance the tiled sweep on or
+ * times the resident blocks, and for one instance the tiled sweep on or
  * off), keeps the fastest, and resets the iterate to the zero start.  With
  * cache_path non-NULL, a result for the same device, precision and instance
  * shape is read from that text file instead of being measured, and new

@@ -289,12 +289,11 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resid
     g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
   }
   g.tile_blocks = 0;
-  // the tiled sweep is used for the FP32 iterate; in FP64 the node-row sweep
-  // measured faster on MI355X (its rows are twice as wide, so each holds more
-  // outstanding loads, and the tile's half-chunk passes re-read lines)
-  // by default only on instances large enough to fill the chip with tiles
+  // by default the tiled sweep runs on instances large enough to fill the
+  // chip with (period, cluster) tiles; small ones are launch-bound and keep
+  // the node-row sweep
   const bool want_tiles = c->tile_mode < 0 ? int64_t(s.N) * s.T >= 65536 : c->tile_mode == 1;
-  if (!c->batch && vec == 4 && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
+  if (!c->batch && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
     const int64_t items = int64_t(s.T) * s.topo.Q;
     const int cap = std::min(kMaxSweepBlocks,
                              std::max(8, int(resident_tile * c->grid_factor) / 8 * 8));
@@ -1171,6 +1170,20 @@ opf_status tape_check(opf_ctx* c) {
   return OPF_OK;
 }
 
+// After a recorded run the control block holds the run's own iteration
+// limits; later opf_iterate / opf_solve calls use the configured ones again.
+opf_status restore_limits(opf_ctx* c) {
+  opf_status s = read_ctls(c);
+  if (s != OPF_OK) return s;
+  Ctl& h = c->h_ctl[0];
+  h.min_iter = c->opt.min_iter;
+  h.max_iter = c->opt.max_iter;
+  h.done = (h.converged || h.numeric_bad || h.iter >= h.max_iter) ? 1 : 0;
+  HIP_TRY(c, hipMemcpyAsync(c->inst[0].ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return OPF_OK;
+}
+
 // Records a forward run.  From the zero start (warm = false): exactly M
 // iterations.  From the current iterate (warm = true): the stopping rule of
 // the options after at least min_iters and at most M iterations.  The
@@ -1227,7 +1240,7 @@ opf_status tape_forward(opf_ctx* c, int M, int C, bool warm, int min_iters, int*
   c->host_iter = c->tape_hist[ran].iter;
   t.ready = true;
   if (n_run) *n_run = ran;
-  return OPF_OK;
+  return restore_limits(c);
 }
 
 template <typename R>
@@ -1280,7 +1293,7 @@ opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_loa
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->host_iter = c->tape_hist[M].iter;
-  return OPF_OK;
+  return restore_limits(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1296,16 +1309,17 @@ constexpr size_t kBlobHead = 256;
 static_assert(sizeof(BlobHead) <= kBlobHead, "blob header");
 
 template <typename R>
-void state_copy(opf_ctx* c, const Inst& s, int cur, char* blob, bool to_blob,
-                const SnapLayout& sl) {
+opf_status state_copy(opf_ctx* c, const Inst& s, int cur, char* blob, bool to_blob,
+                      const SnapLayout& sl) {
   char* arr[kSnapArrays];
   state_arrays<R>(inst_state<R>(s), cur, arr);
   for (int i = 0; i < kSnapArrays; ++i) {
     if (sl.bytes[i] == 0) continue;
     char* b = blob + kBlobHead + sl.off[i];
-    (void)hipMemcpyAsync(to_blob ? b : arr[i], to_blob ? arr[i] : b, sl.bytes[i],
-                         hipMemcpyDefault, c->stream);
+    HIP_TRY(c, hipMemcpyAsync(to_blob ? b : arr[i], to_blob ? arr[i] : b, sl.bytes[i],
+                              hipMemcpyDefault, c->stream));
   }
+  return OPF_OK;
 }
 
 opf_status state_check(opf_ctx* c) {
@@ -1658,7 +1672,7 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    const bool tiles_possible = !c->batch && c->has32 && c->inst[0].topo.Q > 0;
+    const bool tiles_possible = !c->batch && c->inst[0].topo.Q > 0;
     for (int tm = 0; tm <= (tiles_possible ? 1 : 0); ++tm)
     for (int shift = -1; shift <= 1; ++shift) {
       for (double gf : {0.5, 1.0, 2.0}) {
@@ -1787,10 +1801,9 @@ opf_status opf_get_state(opf_ctx* c, void* dst, size_t bytes) {
   char* blob = static_cast<char*>(dst);
   HIP_TRY(c, hipMemcpyAsync(blob, &hd, sizeof(hd), hipMemcpyDefault, c->stream));
   const SnapLayout sl = snap_layout(x, c->precision);
-  if (c->precision == 0)
-    state_copy<double>(c, x, h.cur, blob, true, sl);
-  else
-    state_copy<float>(c, x, h.cur, blob, true, sl);
+  s = c->precision == 0 ? state_copy<double>(c, x, h.cur, blob, true, sl)
+                        : state_copy<float>(c, x, h.cur, blob, true, sl);
+  if (s != OPF_OK) return s;
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return OPF_OK;
@@ -1820,10 +1833,9 @@ opf_status opf_set_state(opf_ctx* c, const void* src, size_t bytes) {
   s = reset_state(c);
   if (s != OPF_OK) return s;
   char* blob = const_cast<char*>(static_cast<const char*>(src));
-  if (hd.precision == 0)
-    state_copy<double>(c, x, 0, blob, false, sl);
-  else
-    state_copy<float>(c, x, 0, blob, false, sl);
+  s = hd.precision == 0 ? state_copy<double>(c, x, 0, blob, false, sl)
+                        : state_copy<float>(c, x, 0, blob, false, sl);
+  if (s != OPF_OK) return s;
   Ctl& h = c->h_ctl[0];
   h.rho_p = hd.rho_p;
   h.rho_th = hd.rho_th;

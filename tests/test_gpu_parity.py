@@ -102,10 +102,11 @@ def compare_fields(s, ref, tol, skip=()):
 
 @pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1",
                                   "curtailable"])
-def test_fp64_iterates_match_oracle(name):
-    say(f"[parity fp64] {name}")
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_fp64_iterates_match_oracle(name, tiles):
+    say(f"[parity fp64] {name} tiles={tiles}")
     ref, hist = oracle_run(name, 200, 0)
-    s = gpu_run(name, 200, "f64", 0)
+    s = gpu_run(name, 200, "f64", 0, sweep_tiles=tiles)
     compare_fields(s, ref, 1e-10)
     gh = s.history()
     assert len(gh) == 200
