@@ -1545,6 +1545,7 @@ opf_status opf_get_field_i(opf_ctx* c, int32_t inst, int32_t field, double* dst,
   size_t need = 0;
   opf_status s = opf_field_size_i(c, inst, field, &need);
   if (s != OPF_OK) return s;
+  if (need == 0) return OPF_OK;  // e.g. line fields of a network without lines
   if (!dst) return fail(c, OPF_E_INVALID, "dst is NULL");
   if (count < need) return fail(c, OPF_E_INVALID, "dst too small: need " + std::to_string(need));
   const Inst& x = c->inst[inst];

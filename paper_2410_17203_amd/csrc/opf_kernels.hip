@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
     const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
     const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
     for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
-    R runW = R(0), runB = R(0);
+    double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
     const R* td_old = A.Td + size_t(t) * Kpp;
     R* td_new = B.Td + size_t(t) * Kpp;
     for (int s0 = 0; s0 < Kpp; s0 += SUB) {
@@ -497,15 +497,15 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
       lds_barrier();
       if (threadIdx.x < cn) {
         for (int v = 0; v < nvc; ++v) {
-          runW += sRw[threadIdx.x * nvc + v];
-          runB += sRb[threadIdx.x * nvc + v];
+          runW += double(sRw[threadIdx.x * nvc + v]);
+          runB += double(sRb[threadIdx.x * nvc + v]);
         }
       }
     }
     if (threadIdx.x < cn) {
       const size_t o = size_t(n0 + threadIdx.x) * T + t;
-      a.st.avgW[o] = runW / R(tp.Kp);
-      a.st.avgTB[o] = runB / R(tp.Kp);
+      a.st.avgW[o] = R(runW / double(tp.Kp));
+      a.st.avgTB[o] = R(runB / double(tp.Kp));
     }
   }
 #pragma unroll

@@ -1,0 +1,94 @@
+"""Degenerate and maximum-size inputs against the oracle: the largest
+contingency count the library accepts (several chunks of contingencies in a
+single line row), a network without lines, and a single node with a
+generator, a load and a battery."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.mp import Options, Solver as Oracle
+from paper_2410_17203_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["P", "TH1", "TH2", "V1", "V2", "U", "PBAR", "THBAR", "PNC", "THNC", "VNC"]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, b):
+    nb = float(torch.linalg.norm(b))
+    na = float(torch.linalg.norm(a - b))
+    return na if nb == 0.0 else na / nb
+
+
+def max_k(K):
+    """The 14-node grid with K contingencies: every non-bridge line outaged
+    once, the rest no-op contingencies."""
+    inst = synth.config("tiny")
+    is_bridge = synth.bridges(inst.N, np.asarray(inst.line_from), np.asarray(inst.line_to))
+    cand = np.nonzero(~is_bridge)[0]
+    out = -np.ones(K, np.int32)
+    out[:len(cand)] = cand
+    inst.K = K
+    inst.outage = out
+    return inst
+
+
+def isolated(N=3, T=4, B=1, seed=0):
+    """N nodes with no lines, each with a generator and a load (node 0 also
+    with a battery): N independent single-node dispatch problems."""
+    rng = np.random.default_rng(seed)
+    f = lambda v: np.asarray(v, np.float64)
+    return synth.Instance(
+        name="isolated", N=N, T=T, K=0,
+        line_from=np.zeros(0, np.int32), line_to=np.zeros(0, np.int32),
+        line_sus=f([]), line_cap=f([]), outage=np.zeros(0, np.int32),
+        gen_node=np.arange(N, dtype=np.int32), gen_c2=rng.uniform(0.01, 0.1, N),
+        gen_c1=rng.uniform(10, 50, N), gen_pmin=np.zeros((N, T)), gen_pmax=np.full((N, T), 3.0),
+        gen_ramp=np.full(N, 0.5),
+        load_node=np.arange(N, dtype=np.int32), load_d=rng.uniform(0.5, 1.5, (N, T)),
+        bat_node=np.zeros(B, np.int32), bat_P=f([0.5] * B), bat_dur=f([4.0] * B),
+        bat_eta=f([0.9] * B), bat_alpha=f([1.0] * B), meta={})
+
+
+CASES = [
+    ("max_k_f32", lambda: max_k(1023), "f32", 1e-4),
+    ("max_k_f64", lambda: max_k(511), "f64", 1e-10),
+    ("no_lines", lambda: isolated(N=3), "f64", 1e-10),
+    ("single_node", lambda: isolated(N=1, T=24), "f64", 1e-10),
+]
+
+
+@pytest.mark.parametrize("tiles", [0, 1])
+@pytest.mark.parametrize("name,builder,dtype,tol", CASES, ids=[c[0] for c in CASES])
+def test_edge_case_iterates_match_oracle(name, builder, dtype, tol, tiles):
+    from paper_2410_17203_amd.binding import Solver
+    say(f"[edge] {name} {dtype} tiles={tiles}")
+    inst = builder()
+    o = Oracle(inst, Options(adapt_every=0, eps=1e-12))
+    o.run(150)
+    ref = o.canonical_state()
+    s = Solver(inst, dtype=dtype, adapt_every=0, eps=1e-12, polish_fp64=0, sweep_tiles=tiles)
+    s.iterate(150)
+    for f in FIELDS:
+        g = s.field(f)
+        assert g.shape == ref[f].shape, f
+        if g.numel():
+            assert rel_err(g, ref[f]) <= tol, (f, rel_err(g, ref[f]))
+    r = s.residuals()
+    assert r["iter"] == 150 and np.isfinite(r["rms_primal"])
+    s.close()
+
+
+def test_contingency_count_above_the_limit_is_rejected():
+    from paper_2410_17203_amd.binding import OpfError, Solver
+    with pytest.raises(OpfError, match="K too large"):
+        Solver(max_k(1024), dtype="f32", polish_fp64=0)
+    with pytest.raises(OpfError, match="K too large"):
+        Solver(max_k(512), dtype="f64")
