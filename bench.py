@@ -360,6 +360,38 @@ def main():
         extra["time_to_tol_final_rms"] = max(r["rms_primal"], r["rms_dual"])
         extra["time_to_tol_threshold"] = r["threshold"]
         log(f"[bench] solve: {r['status']} after {r['iter']} it in {extra['time_to_tol_s']:.1f}s")
+        obj32 = r["objective"]
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        # the same solve with an FP64 iterate throughout, and with BF16-stored
+        # phase duals; objectives compared with the FP64 one (the FP64 path is
+        # the one pinned to the oracle)
+        legs = [("fp64", dict(dtype="f64")),
+                ("bf16_duals", dict(dtype="f32", dual_dtype="bf16", polish_fp64=0))]
+        for label, kw in legs:
+            s = Solver(inst, eps=1e-3, max_iter=args.ttt_max_iter, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.solve()
+            torch.cuda.synchronize()
+            extra[f"{label}_time_to_tol_s"] = time.perf_counter() - t0
+            extra[f"{label}_time_to_tol_iters"] = r["iter"]
+            extra[f"{label}_time_to_tol_converged"] = r["status"] == "OPF_OK"
+            extra[f"{label}_objective"] = r["objective"]
+            log(f"[bench] {label} solve: {r['status']} after {r['iter']} it in "
+                f"{extra[f'{label}_time_to_tol_s']:.1f}s")
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+        ref = extra["fp64_objective"]
+        extra["time_to_tol_objective_rel_err_vs_fp64"] = abs(obj32 - ref) / abs(ref)
+        extra["bf16_duals_objective_rel_err_vs_fp64"] = abs(extra["bf16_duals_objective"] - ref) / abs(ref)
+        s = Solver(inst, dtype="f32", dual_dtype="bf16", polish_fp64=0, **never)
+        el, kt = time_iterations(s, max(args.steps // 2, 1), 5)
+        extra["bf16_duals_iters_per_s"] = max(args.steps // 2, 1) / el
+        extra["bf16_duals_sweep_ms"] = kt["sweep"]["ms"] / max(kt["sweep"]["launches"], 1)
+        log(f"[bench] bf16 duals {extra['bf16_duals_iters_per_s']:.2f} it/s")
         s.close()
         del s
         torch.cuda.empty_cache()
