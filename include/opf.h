@@ -91,12 +91,19 @@ void opf_default_options(opf_options* opt);
  * for T > 1.  Battery parameters are power P, duration (energy = dur * P),
  * charge efficiency eta in (0, 1] and discharge cost alpha >= 0 (Section
  * 2.1, battery).  Every node needs at least one terminal.  Host arrays,
- * caller-owned, copied by opf_load_network. */
+ * caller-owned, copied by opf_load_network.
+ * line_kind (optional, NULL = every line is an AC line): 0 = AC line, 1 = DC
+ * link (HVDC line, Section 2.1): p1 + p2 = 0 and |p2| <= cap with no phase
+ * relation between its terminals, so its susceptance is ignored.  Its prox
+ * takes the clipped midpoint (z2 - z1)/2 of the two power targets as the
+ * flow and leaves both phases at their targets; an outaged DC link carries
+ * no power.  The adjoint (opf_tape_forward, opf_adjoint) rejects networks
+ * with DC links. */
 typedef struct {
   int32_t N, T, K;
   int32_t L;
   const int32_t *line_from, *line_to;
-  const double *line_sus, *line_cap;      /* sus > 0, cap >= 0               */
+  const double *line_sus, *line_cap;      /* sus > 0 (AC lines), cap >= 0    */
   const int32_t* outage;                  /* K entries, distinct or -1       */
   int32_t G;
   const int32_t* gen_node;
@@ -112,6 +119,7 @@ typedef struct {
   int32_t B;
   const int32_t* bat_node;
   const double *bat_P, *bat_dur, *bat_eta, *bat_alpha;
+  const int32_t* line_kind;               /* L entries of 0 or 1, or NULL    */
 } opf_network;
 
 /* Residual record of one iteration (Section 3.3).  Norms are 2-norms over
@@ -257,7 +265,10 @@ opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, op
  * `chunk` (32), chunk c holding contingencies c*chunk .. c*chunk + w - 1 with
  * w = min(chunk, Kpp - c*chunk), so element (t, i, k) is at
  * (t * Kpp + c*chunk) * count + i * w + (k - c*chunk), c = k / chunk.  Td ([T][Kpp])
- * is the half phase difference of each contingency's outaged line; device
+ * is the half phase difference of each contingency's outaged line; Hd
+ * ([T][chunk][Ldc][w], the chunked layout over the Ldc DC links in line
+ * order) holds the half phase difference (theta1 - theta2)/2 of every DC
+ * link, whose Tm is the mean phase as for AC lines; device
  * arrays pnc, thnc, vbar (contingency mean of the phase duals) are
  * [G+D+B][T].  Element types: state_dtype for all but V1, V2 (dual_dtype).
  * Synchronises. */
@@ -266,6 +277,8 @@ typedef struct {
   int32_t state_dtype, dual_dtype;
   int32_t chunk;          /* contingencies per chunk */
   size_t P, Tm, V1, V2, Td, U, W, TB, pnc, thnc, vbar;
+  int32_t Ldc;            /* DC links */
+  size_t Hd;
 } opf_layout;
 opf_status opf_state_layout(opf_ctx* ctx, int32_t instance, opf_layout* out);
 

@@ -50,6 +50,7 @@ import math
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
+import numpy as np
 import torch
 
 DT = torch.float64
@@ -98,6 +99,9 @@ class Network:
         self.deg = torch.zeros(self.N, dtype=DT).index_add_(
             0, self.term_node, torch.ones(self.J, dtype=DT))
         self.sus = _t(inst.line_sus)
+        kind = getattr(inst, "line_kind", None)
+        self.dc = (torch.zeros(self.L, dtype=torch.bool) if kind is None
+                   else torch.as_tensor(np.asarray(kind) == 1))
         self.cap = _t(inst.line_cap) if line_cap is None else line_cap
         outage = torch.as_tensor(inst.outage, dtype=torch.long)
         # contingency k (0 = base case) keeps line l iff l != outage[k-1]
@@ -146,11 +150,15 @@ def prox_generator(x, rho, c2, c1, pmin, pmax):
     return torch.minimum(torch.maximum((rho * x - c1) / (2.0 * c2 + rho), pmin), pmax)
 
 
-def prox_line(z1, z2, xi1, xi2, s, c, rho_p, rho_th):
-    """Prox of the DC line cost I{p1+p2=0} + I{|p2|<=c} + I{p2 = s (th1-th2)}.
+def prox_line(z1, z2, xi1, xi2, s, c, rho_p, rho_th, dc=None):
+    """Prox of the AC line cost I{p1+p2=0} + I{|p2|<=c} + I{p2 = s (th1-th2)}.
 
     Returns (p1, p2, th1, th2).  Where s == 0 (an outaged line) the line
-    carries no power and its phases are unconstrained.
+    carries no power and its phases are unconstrained.  Where dc is True (an
+    HVDC link, Section 2.1: lossless power transfer within the capacity, no
+    phase relation) the cost is I{p1+p2=0} + I{|p2|<=c}: the flow is the
+    clipped midpoint of the two power targets and the phases keep their
+    targets.
     """
     live = s > 0
     s_safe = torch.where(live, s, torch.ones_like(s))
@@ -162,6 +170,11 @@ def prox_line(z1, z2, xi1, xi2, s, c, rho_p, rho_th):
     p2 = torch.where(live, p2, torch.zeros_like(p2))
     th1 = torch.where(live, th1, xi1)
     th2 = torch.where(live, th2, xi2)
+    if dc is not None:
+        p2dc = torch.minimum(torch.maximum(0.5 * (z2 - z1), -c), c)
+        p2 = torch.where(dc, p2dc, p2)
+        th1 = torch.where(dc, xi1, th1)
+        th2 = torch.where(dc, xi2, th2)
     return -p2, p2, th1, th2
 
 
@@ -365,7 +378,7 @@ class Solver:
         s = net.sus[None, :, None] * net.alive[:, :, None]
         c = net.cap[None, :, None] * net.alive[:, :, None]
         p1, p2, th1, th2 = prox_line(x[:, :L], x[:, L:2 * L], y[:, :L], y[:, L:2 * L],
-                                     s, c, rp, rt)
+                                     s, c, rp, rt, net.dc[None, :, None].expand_as(s))
 
         # step 2: non-contingency prox with penalty (K+1) rho at the
         # contingency-averaged targets

@@ -59,6 +59,7 @@ class Network(Structure):
         ("B", c_int32), ("bat_node", POINTER(c_int32)),
         ("bat_P", POINTER(c_double)), ("bat_dur", POINTER(c_double)),
         ("bat_eta", POINTER(c_double)), ("bat_alpha", POINTER(c_double)),
+        ("line_kind", POINTER(c_int32)),
     ]
 
 
@@ -87,7 +88,8 @@ class Layout(Structure):
                 ("L", c_int32), ("Jnc", c_int32), ("state_dtype", c_int32),
                 ("dual_dtype", c_int32), ("chunk", c_int32),
                 *[(n, c_size_t) for n in ["P", "Tm", "V1", "V2", "Td", "U", "W", "TB", "pnc",
-                                          "thnc", "vbar"]]]
+                                          "thnc", "vbar"]],
+                ("Ldc", c_int32), ("Hd", c_size_t)]
 
 
 class OpfError(RuntimeError):
@@ -196,6 +198,9 @@ class NetworkArrays:
         n.bat_dur = p(inst.bat_dur, f64, c_double)
         n.bat_eta = p(inst.bat_eta, f64, c_double)
         n.bat_alpha = p(inst.bat_alpha, f64, c_double)
+        kind = getattr(inst, "line_kind", None)
+        if kind is not None:
+            n.line_kind = p(kind, i32, c_int32)
         self.net = n
 
 
@@ -311,7 +316,7 @@ class Solver:
         """Zero-copy views of one array of the current iterate, valid until
         the next iteration.  Line and node arrays: a list with one [T, count,
         w] tensor per chunk of contingencies (layout()['chunk'] wide, the last one
-        narrower); Td [T, Kpp];
+        narrower); Hd (DC links) likewise over layout()['Ldc'] links; Td [T, Kpp];
         device arrays [Jnc, T]."""
         torch = self.torch
         lay = self.layout(instance)
@@ -325,7 +330,7 @@ class Solver:
             shape = (T, Kpp) if name == "Td" else (J, T)
             n = int(np.prod(shape))
             return self.ws[lay[name]:lay[name] + n * esize].view(dtype).view(shape)
-        count = L if name in ("P", "Tm", "V1", "V2") else N
+        count = {"P": L, "Tm": L, "V1": L, "V2": L, "Hd": lay["Ldc"]}.get(name, N)
         flat = self.ws.view(dtype) if self.ws.numel() % esize == 0 else None
         out = []
         ch = lay["chunk"]

@@ -515,9 +515,10 @@ __device__ inline R gen_target(R X, R c1, R c2, R rho_hat) {
 
 // Step 1 for one line and one 16-byte vector of contingencies (Section 4.2,
 // DC line prox with the per-contingency susceptance and capacity of the N-1
-// model), preceded by the deferred scaled-price update v += theta - thetabar
-// of the previous iteration and the pending penalty rescale.  Both end
-// nodes of a line call this with identical inputs.
+// model, or the HVDC link prox when dc: Hd then holds the link's old half
+// phase differences), preceded by the deferred scaled-price update
+// v += theta - thetabar of the previous iteration and the pending penalty
+// rescale.  Both end nodes of a line call this with identical inputs.
 template <typename R, int VEC>
 struct LineOut {
   R p[VEC], tm[VEC], v1[VEC], v2[VEC], half[VEC];
@@ -530,8 +531,9 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
                                           const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
                                           const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
                                           const Vec<int32_t, VEC>& ok, int l, const R* td_old,
-                                          int k0, int Kp, R s, R cap, R rp, R rt, R sv,
-                                          LineOut<R, VEC>& o) {
+                                          bool dc, const Vec<R, VEC>& Hd, int k0, int Kp, R s,
+                                          R cap, R rp, R rt, R sv, LineOut<R, VEC>& o) {
+  if (dc) s = R(1);  // a DC link has no susceptance; keep the unused weights finite
   const R inv2s = R(0.5) / s;
   const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;  // 2 rho_p + rho_th / (2 s^2)
   const R ca = rp / den;                                // weight of z2 - z1
@@ -539,7 +541,7 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
     const bool outg = ok.x[e] == l;
-    const R half = outg ? td_old[e] : P.x[e] * inv2s;
+    const R half = dc ? Hd.x[e] : (outg ? td_old[e] : P.x[e] * inv2s);
     const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
     R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
     R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
@@ -550,6 +552,10 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
     R pn, hn, u;
     if (outg) {
       u = pn = R(0);
+      hn = R(0.5) * (xi1 - xi2);
+    } else if (dc) {  // HVDC link: flow at the clipped midpoint, phases at their targets
+      u = R(0.5) * (z2 - z1);
+      pn = clampv(u, -cap, cap);
       hn = R(0.5) * (xi1 - xi2);
     } else {
       u = ca * (z2 - z1) + cb * (xi1 - xi2);

@@ -44,7 +44,7 @@ struct Layout {
 };
 
 struct BufOffsets {
-  size_t P, Tm, V1, V2, Td, U, W, TB;
+  size_t P, Tm, V1, V2, Td, Hd, U, W, TB;
 };
 struct StateOffsets {
   BufOffsets buf[2];
@@ -60,6 +60,7 @@ struct Timed {
 // One loaded instance.
 struct Inst {
   int N = 0, T = 0, K = 0, Kp = 0, Kpp = 0, L = 0, G = 0, D = 0, B = 0, Jnc = 0, nR = 0;
+  int Ldc = 0;  // DC links
   double eps_eff = 0.0, rms_norm = 1.0;
   Topo topo{};
   Geom geom64{}, geom32{};
@@ -72,10 +73,11 @@ struct Inst {
 };
 
 // Offsets of everything one instance holds in the workspace.
-// Snapshot of the iterate of one precision: 15 arrays (line P, Tm, V1, V2,
+// Snapshot of the iterate of one precision: 16 arrays (line P, Tm, V1, V2,
 // outaged half difference, node U, W, thetabar, the two node means, device
-// power/phase/phase dual, ramp and battery inner states), packed.
-constexpr int kSnapArrays = 15;
+// power/phase/phase dual, ramp and battery inner states, DC link half
+// differences), packed.
+constexpr int kSnapArrays = 16;
 struct SnapLayout {
   size_t off[kSnapArrays];
   size_t bytes[kSnapArrays];
@@ -106,7 +108,7 @@ struct InstPlan {
       nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
       bat_eta, bat_alpha;
   size_t part_sweep, part_nc;
-  size_t clus_n0, tl_ptr, tl, tcsr;
+  size_t clus_n0, tl_ptr, tl, tcsr, line_dc;
   StateOffsets o64{}, o32{};
 };
 
@@ -201,7 +203,10 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
   for (int l = 0; l < n->L; ++l) {
     if (!node_ok(n->line_from[l]) || !node_ok(n->line_to[l]))
       return fail(c, OPF_E_INVALID, "line node index out of range at line " + std::to_string(l));
-    if (!(n->line_sus[l] > 0.0) || !finite(n->line_sus[l]))
+    const int kind = n->line_kind ? n->line_kind[l] : 0;
+    if (kind != 0 && kind != 1)
+      return fail(c, OPF_E_INVALID, "line kind must be 0 (AC) or 1 (DC) at line " + std::to_string(l));
+    if (kind == 0 && (!(n->line_sus[l] > 0.0) || !finite(n->line_sus[l])))
       return fail(c, OPF_E_INVALID, "line susceptance must be finite and > 0 at line " + std::to_string(l));
     if (!(n->line_cap[l] >= 0.0) || !finite(n->line_cap[l]))
       return fail(c, OPF_E_INVALID, "line capacity must be finite and >= 0 at line " + std::to_string(l));
@@ -261,6 +266,9 @@ void set_sizes(Inst& s, const opf_network* n) {
   s.D = n->D;
   s.B = n->B;
   s.Jnc = n->G + n->D + n->B;
+  s.Ldc = 0;
+  if (n->line_kind)
+    for (int l = 0; l < n->L; ++l) s.Ldc += n->line_kind[l] == 1;
   s.nR = 0;
   if (n->T > 1)
     for (int g = 0; g < n->G; ++g)
@@ -316,6 +324,7 @@ void state_offsets(const Inst& s, Layout& lay, StateOffsets& o) {
     b.V1 = lay.take(line * sizeof(VT));
     b.V2 = lay.take(line * sizeof(VT));
     b.Td = lay.take(size_t(s.T) * s.Kpp * sizeof(R));
+    b.Hd = lay.take(size_t(s.Ldc) * s.T * s.Kpp * sizeof(R));
     b.U = lay.take(node * sizeof(R));
     b.W = lay.take(node * sizeof(R));
     b.TB = lay.take(node * sizeof(R));
@@ -342,6 +351,7 @@ State<R, VT> state_ptrs(char* ws, const StateOffsets& o) {
     d.V1 = reinterpret_cast<VT*>(ws + b.V1);
     d.V2 = reinterpret_cast<VT*>(ws + b.V2);
     d.Td = reinterpret_cast<R*>(ws + b.Td);
+    d.Hd = reinterpret_cast<R*>(ws + b.Hd);
     d.U = reinterpret_cast<R*>(ws + b.U);
     d.W = reinterpret_cast<R*>(ws + b.W);
     d.TB = reinterpret_cast<R*>(ws + b.TB);
@@ -374,6 +384,7 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
   p.tl_ptr = L.take((Ni + 1) * 4);
   p.tl = L.take(2 * Li * 16);
   p.tcsr = L.take(2 * Li * 4);
+  p.line_dc = L.take(Li * 4);
   p.nc_node = L.take(size_t(s.Jnc) * 4);
   p.ramp_idx = L.take(Gi * 4);
   p.gen_c2 = L.take(Gi * 8);
@@ -625,6 +636,8 @@ opf_status refresh_geometry(opf_ctx* c) {
     t.dev_prefix = c->d_dev_prefix;
     t.grp_prefix = grp;
     t.n_inst = n;
+    t.any_dc = 0;
+    for (const Inst& x : c->inst) t.any_dc |= x.Ldc > 0 ? 1 : 0;
     t.total_dev = dev[n];
     t.total_grps = total_grps;
     int nb = std::max(8, round8(std::min<int64_t>(total_grps, kMaxSweepBlocks)));
@@ -798,6 +811,18 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
       for (int g = 0; g < G; ++g)
         if (n->gen_ramp[g] > 0.0 && std::isfinite(n->gen_ramp[g])) ramp_idx[g] = r++;
   }
+  // DC links: index among them, and a unit susceptance in place of the
+  // ignored one so that the unused AC weights stay finite
+  std::vector<int32_t> line_dc(L, -1);
+  std::vector<double> sus(n->line_sus, n->line_sus + L);
+  {
+    int m = 0;
+    for (int l = 0; l < L; ++l)
+      if (n->line_kind && n->line_kind[l] == 1) {
+        line_dc[l] = m++;
+        sus[l] = 1.0;
+      }
+  }
   double lsum = 0.0;
   for (size_t i = 0; i < size_t(D) * T; ++i) lsum += n->load_d[i] * n->load_d[i];
   const double load_rms = (size_t(D) * T > 0) ? std::sqrt(lsum / double(size_t(D) * T)) : 1.0;
@@ -808,7 +833,8 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   };
   HIP_TRY(c, up(p.line_from, n->line_from, size_t(L) * 4));
   HIP_TRY(c, up(p.line_to, n->line_to, size_t(L) * 4));
-  HIP_TRY(c, up(p.sus, n->line_sus, size_t(L) * 8));
+  HIP_TRY(c, up(p.sus, sus.data(), size_t(L) * 8));
+  HIP_TRY(c, up(p.line_dc, line_dc.data(), size_t(L) * 4));
   HIP_TRY(c, up(p.cap, n->line_cap, size_t(L) * 8));
   HIP_TRY(c, up(p.outage_k, outage_k.data(), size_t(Kpp) * 4));
   HIP_TRY(c, up(p.node_lptr, lptr.data(), size_t(N + 1) * 4));
@@ -854,6 +880,8 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   tp.tl_ptr = reinterpret_cast<const int32_t*>(ws + p.tl_ptr);
   tp.tl = reinterpret_cast<const int4*>(ws + p.tl);
   tp.tcsr = reinterpret_cast<const int32_t*>(ws + p.tcsr);
+  tp.Ldc = s.Ldc;
+  tp.line_dc = reinterpret_cast<const int32_t*>(ws + p.line_dc);  // all -1 without DC links
   tp.nc_node = reinterpret_cast<const int32_t*>(ws + p.nc_node);
   tp.ramp_idx = reinterpret_cast<const int32_t*>(ws + p.ramp_idx);
   tp.gen_c2 = reinterpret_cast<const double*>(ws + p.gen_c2);
@@ -1007,7 +1035,7 @@ SnapLayout snap_layout(const Inst& s, int precision) {
       line, line, line, line, size_t(s.T) * s.Kpp * S, node, node, node,
       size_t(s.N) * s.T * S, size_t(s.N) * s.T * S, size_t(s.Jnc) * s.T * S,
       size_t(s.Jnc) * s.T * S, size_t(s.Jnc) * s.T * S, 4 * size_t(s.nR) * s.T * S,
-      6 * size_t(s.B) * s.T * S};
+      6 * size_t(s.B) * s.T * S, size_t(s.Ldc) * s.T * s.Kpp * S};
   SnapLayout sl{};
   Layout L;
   for (int i = 0; i < kSnapArrays; ++i) {
@@ -1065,7 +1093,7 @@ void state_arrays(const State<R, R>& st, int cur, char* (&out)[kSnapArrays]) {
       reinterpret_cast<char*>(st.avgW), reinterpret_cast<char*>(st.avgTB),
       reinterpret_cast<char*>(st.pnc), reinterpret_cast<char*>(st.thnc),
       reinterpret_cast<char*>(st.vbar), reinterpret_cast<char*>(st.ramp_st),
-      reinterpret_cast<char*>(st.bat_st)};
+      reinterpret_cast<char*>(st.bat_st), reinterpret_cast<char*>(b.Hd)};
   for (int i = 0; i < kSnapArrays; ++i) out[i] = a[i];
 }
 
@@ -1113,6 +1141,7 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
   a.A.V1 = sp(2);
   a.A.V2 = sp(3);
   a.A.Td = sp(4);
+  a.A.Hd = nullptr;  // no DC links on a tape
   a.A.U = sp(5);
   a.A.W = sp(6);
   a.A.TB = sp(7);
@@ -1167,6 +1196,7 @@ opf_status tape_check(opf_ctx* c) {
   if (c->bf16_duals) return fail(c, OPF_E_INVALID, "the adjoint needs FP32 or FP64 duals, not BF16");
   if (c->opt.inner_iters > kMaxAdjInner)
     return fail(c, OPF_E_INVALID, "the adjoint supports inner_iters <= 32");
+  if (c->inst[0].Ldc > 0) return fail(c, OPF_E_INVALID, "the adjoint does not support DC links");
   return OPF_OK;
 }
 
@@ -1304,6 +1334,7 @@ struct BlobHead {
   int32_t version, precision, N, T, K, L, Jnc, nR, B;
   double rho_p, rho_th;
   double su, sv;  // pending rescale ratios (deferred to the next iteration)
+  int32_t Ldc;
 };
 constexpr size_t kBlobHead = 256;
 static_assert(sizeof(BlobHead) <= kBlobHead, "blob header");
@@ -1742,6 +1773,7 @@ opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
   out->state_dtype = c->precision == 0 ? OPF_F64 : OPF_F32;
   out->dual_dtype = c->precision == 0 ? OPF_F64 : (c->bf16_duals ? OPF_BF16 : OPF_F32);
   out->chunk = kChunk;
+  out->Ldc = x.Ldc;
   auto off = [&](const void* p) { return size_t(static_cast<const char*>(p) - c->ws); };
   auto fill = [&](const auto& st) {
     const auto& b = st.buf[cur];
@@ -1750,6 +1782,7 @@ opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
     out->V1 = off(b.V1);
     out->V2 = off(b.V2);
     out->Td = off(b.Td);
+    out->Hd = off(b.Hd);
     out->U = off(b.U);
     out->W = off(b.W);
     out->TB = off(b.TB);
@@ -1795,6 +1828,7 @@ opf_status opf_get_state(opf_ctx* c, void* dst, size_t bytes) {
   hd.Jnc = x.Jnc;
   hd.nR = x.nR;
   hd.B = x.B;
+  hd.Ldc = x.Ldc;
   hd.rho_p = h.rho_p;
   hd.rho_th = h.rho_th;
   hd.su = h.su;
@@ -1821,7 +1855,7 @@ opf_status opf_set_state(opf_ctx* c, const void* src, size_t bytes) {
   if (std::memcmp(hd.magic, "OPFSTATE", 8) != 0 || hd.version != 1)
     return fail(c, OPF_E_INVALID, "not a state exported by opf_get_state");
   if (hd.N != x.N || hd.T != x.T || hd.K != x.K || hd.L != x.L || hd.Jnc != x.Jnc ||
-      hd.nR != x.nR || hd.B != x.B)
+      hd.nR != x.nR || hd.B != x.B || hd.Ldc != x.Ldc)
     return fail(c, OPF_E_INVALID, "state was exported from a network of another shape");
   if (!(hd.precision == 0 ? c->has64 : c->has32))
     return fail(c, OPF_E_INVALID, "state precision is not held by this context");

@@ -16,7 +16,9 @@
 // Time is outermost.  FP32 and FP64 iterates use the same element indices.
 // A line's two phases are stored as their mean Tm; the half difference is
 // P / (2 b) for a live line and, for the one outaged line of contingency k,
-// a separate [T][Kpp] array Td.  Line and node arrays are double-buffered
+// a separate [T][Kpp] array Td.  A DC link has no phase relation, so its
+// half difference is state of its own: Hd [T][chunk][Ldc][w] over the DC
+// links in line order.  Line and node arrays are double-buffered
 // (the sweep reads one buffer and writes the other).
 #pragma once
 
@@ -117,6 +119,9 @@ struct Topo {
   const int32_t* tl_ptr;      // [Q+1] range of each cluster's lines in tl
   const int4* tl;             // (line, local from node or -1, local to node or -1, far node or -1)
   const int32_t* tcsr;        // parallel to node_lterm: 2 * (index in the cluster's tl) + end
+  // DC links (Ldc = 0: none; the sweeps then run a variant that never reads line_dc)
+  int32_t Ldc;
+  const int32_t* line_dc;     // [L] index among the DC links, -1 for an AC line
 };
 
 // Double-buffered part of the iterate.
@@ -127,6 +132,7 @@ struct Buf {
   VT* V1;
   VT* V2;
   R* Td;      // [T][Kpp]
+  R* Hd;      // [T][chunk][Ldc][w]
   R* U;
   R* W;
   R* TB;
@@ -179,6 +185,7 @@ struct BatchTab {
   const int64_t* grp_prefix;  // [n_inst + 1]
   int32_t n_inst;
   int32_t n_sweep_blocks;
+  int32_t any_dc;             // some instance holds DC links
   int64_t total_dev;
   int64_t total_grps;
 };

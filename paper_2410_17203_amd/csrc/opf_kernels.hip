@@ -101,7 +101,8 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
 // Steps 1 and 3 for one (period, node) row and one 16-byte vector of
 // contingencies.  acc: FP64 residual partials [sum |n| pbar^2, sum theta
 // tilde^2, sum |n| dpbar^2, sum |n| dthetabar^2, sum over lines of 2 dP^2].
-template <typename R, typename VT>
+// DC: the instance may hold DC links (compiled out otherwise).
+template <typename R, typename VT, bool DC>
 __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, const Buf<R, VT>& B,
                                  int row, int v, int q0, int q1, bool check, R rp, R rt, R sv,
                                  double (&acc)[5], R& sumw, R& sumb) {
@@ -152,10 +153,15 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       const int l = term[u].x >> 1;
       const bool to_end = term[u].x & 1;  // this node is the line's terminal-2 node
       const size_t ol = ck_off(t, l, k0, tp.L, tp.Kpp);
+      // (a batch runs this variant for every instance, with or without links)
+      const int dci = (DC && tp.line_dc) ? tp.line_dc[l] : -1;
+      const size_t oh = dci >= 0 ? ck_off(t, dci, k0, tp.Ldc, tp.Kpp) : 0;
+      VR Hx{};
+      if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
       LineOut<R, VEC> o;
       line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo, to_end ? Wo : Wx[u],
-                            to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l, td_old, k0, tp.Kp,
-                            R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+                            to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l, td_old, dci >= 0, Hx,
+                            k0, tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
       if (!to_end) {  // the from node stores the line's new state
         VR Pn, Tn;
         VV V1n, V2n;
@@ -175,6 +181,12 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
         st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
         st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
         st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+        if (dci >= 0) {
+          VR Hn;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) Hn.x[e] = o.half[e];
+          *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+        }
       }
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
@@ -241,7 +253,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
 // of two, at most one wavefront); each lane takes the row's 16-byte vectors
 // q, q + lanes_per_row, ...  The contingency sums of a row are reduced with
 // shuffles inside its lane group (no LDS, no barrier).
-template <typename R, typename VT>
+template <typename R, typename VT, bool DC>
 __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a) {
   Ctl* ctl = a.g.ctl;
   if (ctl->done) return;
@@ -267,7 +279,7 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, DC>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
@@ -299,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // registers of the thread that owns the node across the chunks.  Tiles of
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
-template <typename R, typename VT>
+template <typename R, typename VT, bool DC>
 __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
@@ -381,9 +393,14 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
         }
         const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+        const int dci = (DC && tp.line_dc) ? tp.line_dc[l] : -1;
+        const size_t oh =
+            dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC : 0;
+        VR Hx{};
+        if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
         LineOut<R, VEC> o;
-        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
-                              R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, dci >= 0, Hx, k0,
+                              tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
         if (e.y >= 0) {  // the cluster holding the from node stores the line
           VR Pn, Tn;
           VV V1n, V2n;
@@ -403,6 +420,12 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
           st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
           st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+          if (dci >= 0) {
+            VR Hn;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
+            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+          }
         }
         VR Po, To, Ho;
 #pragma unroll
@@ -711,7 +734,7 @@ __global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
   }
 }
 
-template <typename R, typename VT>
+template <typename R, typename VT, bool DC>
 __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
@@ -738,7 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, DC>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
@@ -809,7 +832,10 @@ __global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, do
       return;
     }
     const bool outg = tp.outage_k[k] == l;
-    const double half = outg ? double(C.Td[size_t(t) * tp.Kpp + k]) : P * (0.5 / tp.sus[l]);
+    const int dci = tp.line_dc ? tp.line_dc[l] : -1;
+    const double half = dci >= 0 ? double(C.Hd[ck_off(t, dci, k, tp.Ldc, tp.Kpp)])
+                        : outg   ? double(C.Td[size_t(t) * tp.Kpp + k])
+                                 : P * (0.5 / tp.sus[l]);
     const double th1 = double(C.Tm[o]) + half, th2 = double(C.Tm[o]) - half;
     if (field == 1) dst[i] = th1;
     if (field == 2) dst[i] = th2;
@@ -871,17 +897,25 @@ int sweep_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<R, VT>, kBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep<R, VT, false>, kBlock, 0) != hipSuccess)
     return 0;
   return cus * per;
 }
 
 template <typename R, typename VT>
 void launch_sweep(const KArgs<R, VT>& a, hipStream_t s) {
-  if (a.g.tile_blocks > 0)
-    k_sweep_tile<R, VT><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
-  else
-    k_sweep<R, VT><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+  const bool dc = a.tp.Ldc > 0;
+  if (a.g.tile_blocks > 0) {
+    if (dc)
+      k_sweep_tile<R, VT, true><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
+    else
+      k_sweep_tile<R, VT, false><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
+  } else {
+    if (dc)
+      k_sweep<R, VT, true><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+    else
+      k_sweep<R, VT, false><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
+  }
 }
 
 // Blocks of the tiled sweep resident at once on the current device.
@@ -890,7 +924,7 @@ int tile_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile<R, VT>, kTileBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile<R, VT, false>, kTileBlock, 0) !=
       hipSuccess)
     return 0;
   return cus * per;
@@ -940,6 +974,7 @@ void launch_widen(const KArgs<float, VT>& a, const KArgs<double, double>& b, hip
     widen(x.V1, y.V1, line, s);
     widen(x.V2, y.V2, line, s);
     widen(x.Td, y.Td, int64_t(tp.T) * tp.Kpp, s);
+    widen(x.Hd, y.Hd, int64_t(tp.Ldc) * tp.T * tp.Kpp, s);
     widen(x.U, y.U, node, s);
     widen(x.W, y.W, node, s);
     widen(x.TB, y.TB, node, s);
@@ -969,7 +1004,10 @@ void launch_batch_iter_devices(const BatchTab& tab, int max_T, hipStream_t s) {
 
 template <typename R, typename VT>
 void launch_batch_iter_sweep(const BatchTab& tab, hipStream_t s) {
-  k_sweep_batch<R, VT><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
+  if (tab.any_dc)
+    k_sweep_batch<R, VT, true><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
+  else
+    k_sweep_batch<R, VT, false><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
 }
 
 template <typename R, typename VT>
@@ -987,7 +1025,7 @@ int sweep_batch_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_batch<R, VT>, kBlock, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_batch<R, VT, false>, kBlock, 0) != hipSuccess)
     return 0;
   return cus * per;
 }

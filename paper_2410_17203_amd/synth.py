@@ -73,6 +73,7 @@ class Instance:
     bat_dur: np.ndarray
     bat_eta: np.ndarray
     bat_alpha: np.ndarray
+    line_kind: Optional[np.ndarray] = None  # [L] 0 = AC line, 1 = DC link; None = all AC
     meta: Dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -413,4 +414,44 @@ def with_curtailable_loads(inst: Instance, cost: float = 500.0) -> Instance:
         gen_ramp=np.r_[inst.gen_ramp, np.full(D, np.inf)],
         load_node=np.zeros(0, np.int32),
         load_d=np.zeros((0, T)),
+    )
+
+
+def with_dc_links(inst: Instance, count: int = 3, seed: int = 0, outage_first: bool = True,
+                  cap=(1.0, 3.0)) -> Instance:
+    """The same network plus `count` HVDC links (Section 2.1; the paper's
+    western-interconnect case has 3 among about 1150 lines) appended after
+    the AC lines.  Each joins two seed-chosen nodes at least N/4 apart in the
+    Hilbert node order (long-distance links), with capacity U[cap]; a DC
+    link's susceptance is ignored (stored as 10).  With outage_first and
+    K >= 1, contingency 1 removes the first DC link instead of its AC line.
+    Every existing N-1-feasible dispatch stays feasible with the links idle."""
+    import dataclasses as _dc
+    rng = np.random.default_rng([seed, 0xDC])
+    N, L = int(inst.N), len(inst.line_from)
+    frm, to = [], []
+    seen = set(zip(np.asarray(inst.line_from).tolist(), np.asarray(inst.line_to).tolist()))
+    while len(frm) < count:
+        a, b = sorted(int(x) for x in rng.integers(0, N, 2))
+        if b - a < max(1, N // 4) or (a, b) in seen:
+            if N < 4:  # tiny grids: any distinct pair
+                if a == b:
+                    continue
+            else:
+                continue
+        seen.add((a, b))
+        frm.append(a)
+        to.append(b)
+    kind0 = np.zeros(L, np.int32) if inst.line_kind is None else np.asarray(inst.line_kind, np.int32)
+    outage = np.asarray(inst.outage, np.int32).copy()
+    if outage_first and int(inst.K) >= 1 and count >= 1:
+        outage[0] = L
+    return _dc.replace(
+        inst,
+        line_from=np.r_[inst.line_from, frm].astype(np.int32),
+        line_to=np.r_[inst.line_to, to].astype(np.int32),
+        line_sus=np.r_[inst.line_sus, np.full(count, 10.0)],
+        line_cap=np.r_[inst.line_cap, rng.uniform(cap[0], cap[1], count)],
+        outage=outage,
+        line_kind=np.r_[kind0, np.ones(count, np.int32)],
     )

@@ -37,6 +37,7 @@ def batch_instances():
         out.append(synth.make_instance(f"b{i}", N=N, L=int(round(1.4 * N)), G=max(2, N // 5),
                                        D=int(0.8 * N), B=max(1, N // 25), T=T, K=K,
                                        seed=900 + i))
+    out[2] = synth.with_dc_links(out[2], 3, seed=2)  # DC links beside AC-only instances
     return out
 
 

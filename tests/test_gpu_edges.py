@@ -92,3 +92,31 @@ def test_contingency_count_above_the_limit_is_rejected():
         Solver(max_k(1024), dtype="f32", polish_fp64=0)
     with pytest.raises(OpfError, match="K too large"):
         Solver(max_k(512), dtype="f64")
+
+
+def test_dc_link_rules_are_enforced():
+    """Line kinds other than 0/1 are rejected; the adjoint rejects DC links;
+    a DC link's susceptance is ignored (any value, even 0, gives the same
+    iterate)."""
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import OpfError, Solver
+    base = synth.make_instance("dc_rules", N=12, L=17, G=4, D=8, B=1, T=4, K=3, seed=5)
+    inst = synth.with_dc_links(base, 2, seed=1)
+    bad = inst.copy()
+    bad.line_kind = bad.line_kind.copy()
+    bad.line_kind[0] = 2
+    with pytest.raises(OpfError, match="line kind"):
+        Solver(bad, dtype="f64")
+    s = Solver(inst, dtype="f64", polish_fp64=0)
+    with pytest.raises(OpfError, match="DC links"):
+        s.tape_forward(10, 5)
+    s.iterate(20)
+    other = inst.copy()
+    other.line_sus = np.asarray(other.line_sus, float).copy()
+    other.line_sus[inst.line_kind == 1] = 0.0
+    t = Solver(other, dtype="f64", polish_fp64=0)
+    t.iterate(20)
+    for f in ["P", "TH1", "TH2", "U"]:
+        assert torch.equal(s.field(f), t.field(f)), f
+    s.close()
+    t.close()

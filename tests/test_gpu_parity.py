@@ -57,6 +57,11 @@ def make(name):
         base = synth.make_instance("curt", N=30, L=45, G=6, D=20, B=2, T=6, K=4, seed=41)
         base.gen_pmax = np.asarray(base.gen_pmax) * 0.5  # some demand goes unserved
         return synth.with_curtailable_loads(base, cost=50.0)
+    if name == "hvdc":  # DC links (Section 2.1), one outaged by contingency 1; two chunks
+        base = synth.make_instance("hvdc", N=30, L=60, G=8, D=20, B=3, T=6, K=37, seed=77)
+        return synth.with_dc_links(base, 4, seed=5)
+    if name == "tiny_dc":  # binding and free DC links in the tiny grid
+        return synth.with_dc_links(synth.config("tiny"), 3, seed=3, cap=(0.05, 0.2))
     if name == "no_batteries_T1":
         return synth.make_instance("nb", N=25, L=35, G=5, D=18, B=0, T=1, K=9, seed=25)
     raise KeyError(name)
@@ -101,7 +106,7 @@ def compare_fields(s, ref, tol, skip=()):
 
 
 @pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1",
-                                  "curtailable"])
+                                  "curtailable", "hvdc"])
 @pytest.mark.parametrize("tiles", [0, 1])
 def test_fp64_iterates_match_oracle(name, tiles):
     say(f"[parity fp64] {name} tiles={tiles}")
@@ -123,7 +128,7 @@ def test_fp64_iterates_match_oracle(name, tiles):
 
 @pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("name", ["medium", "wide_T", "edge", "no_batteries_T1", "hub",
-                                  "curtailable"])
+                                  "curtailable", "hvdc"])
 def test_fp32_iterates_match_oracle(name, tiles):
     """FP32 iterate with the node-row sweep and with the sweep over clusters
     of consecutive nodes (several chunks of contingencies, a ragged last
@@ -164,6 +169,28 @@ def test_solve_matches_oracle_on_tiny():
     assert rg["status"] == "OPF_OK" and ro.converged
     assert rg["iter"] == ro.iter
     assert abs(rg["objective"] - ro.objective) <= 1e-5 * abs(ro.objective)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dc_link_solve_matches_oracle(dtype):
+    """Solve with DC links to 1e-6: FP64 in the oracle's iteration count; FP32
+    switching to FP64 near the tolerance (the DC link half phase differences
+    are widened with the rest of the iterate)."""
+    say(f"[parity solve] tiny_dc {dtype}")
+    inst = make("tiny_dc")
+    o = Oracle(inst, Options(eps=1e-6, max_iter=20000))
+    ro = o.solve()
+    from paper_2410_17203_amd.binding import Solver
+    s = Solver(inst, dtype=dtype, eps=1e-6, max_iter=20000, polish_factor=10.0)
+    rg = s.solve()
+    assert rg["status"] == "OPF_OK" and ro.converged
+    assert rg["precision"] == 0
+    if dtype == "f64":
+        assert rg["iter"] == ro.iter
+    assert abs(rg["objective"] - ro.objective) <= 1e-5 * abs(ro.objective)
+    th = s.field("TH1")
+    assert float(th.abs().max()) > 0  # AC lines still carry phases
     s.close()
 
 

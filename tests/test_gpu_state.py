@@ -123,3 +123,35 @@ def test_import_rejects_mismatched_state():
         a.set_state(bad)
     a.close()
     b.close()
+
+
+def test_dc_link_state_view_and_continuation():
+    """With DC links the iterate holds their half phase differences (view
+    'Hd', equal to (TH1 - TH2)/2 of each link in every contingency), and an
+    exported state carries them: the continuation is bitwise identical."""
+    from paper_2410_17203_amd.binding import Solver
+    say("[state] DC links")
+    inst = synth.with_dc_links(small(), 3, seed=9)
+    dcl = np.nonzero(inst.line_kind == 1)[0]
+    opts = dict(adapt_every=0, polish_fp64=0)
+    a = Solver(inst, dtype="f64", **opts)
+    a.iterate(30)
+    lay = a.layout()
+    assert lay["Ldc"] == 3
+    hd = torch.cat(a.view("Hd"), dim=2).double().cpu()[:, :, :inst.K + 1]   # [T, Ldc, K+1]
+    half = 0.5 * (a.field("TH1") - a.field("TH2"))[:, dcl, :]                # [K+1, Ldc, T]
+    # TH1, TH2 = Tm +- Hd, so (TH1 - TH2)/2 recovers Hd up to the rounding of Tm +- Hd
+    torch.testing.assert_close(hd.permute(2, 1, 0), half, rtol=0, atol=1e-15)
+    assert float(half.abs().max()) > 0
+    blob = a.get_state()
+    a.iterate(25)
+    b = Solver(inst, dtype="f64", **opts)
+    b.set_state(blob)
+    b.iterate(25)
+    for f in ["P", "TH1", "TH2", "V1", "U", "THBAR", "PNC"]:
+        assert torch.equal(a.field(f), b.field(f)), f
+    c = Solver(synth.with_dc_links(small(), 2, seed=9), dtype="f64", **opts)
+    with pytest.raises(Exception, match="another shape"):
+        c.set_state(blob)
+    for x in (a, b, c):
+        x.close()

@@ -149,6 +149,57 @@ def test_two_node_analytic_dispatch(cap):
         assert abs(lm[1] - lm[0]) > 0.5  # congestion separates the prices
 
 
+@pytest.mark.parametrize("cap", [10.0, 1.0])
+def test_two_node_dc_link_dispatch(cap):
+    """The same two-node economic dispatch through an HVDC link (Section 2.1):
+    the dispatch, flow and prices match the closed form, and with no phase
+    relation anywhere every phase stays exactly zero."""
+    c2, c1, pmax, d = (0.5, 0.25), (1.0, 2.0), (5.0, 5.0), 3.0
+    inst = synth.two_node(d=d, c2=c2, c1=c1, pmax=pmax, sus=2.0, cap=cap)
+    inst.line_kind = np.array([1], np.int32)
+    s = Solver(inst, Options(eps=1e-10, eps_relative=False, max_iter=200000))
+    r = s.solve()
+    assert r.converged
+    p1, p2, _, lmp = _two_node_analytic(c2, c1, pmax, d, cap, 2.0)
+    np.testing.assert_allclose(s.dispatch()[:2, 0].numpy(), [p1, p2], atol=1e-7)
+    assert abs(float(s.p[0, 1, 0]) - p1) < 1e-7
+    assert float(s.th.abs().max()) == 0.0
+    np.testing.assert_allclose(s.lmp()[:, 0].numpy(), lmp, rtol=1e-6)
+
+
+def test_dc_links_satisfy_optimality():
+    """HVDC links in a meshed grid (T = 1, K = 0).  At the converged iterate
+    (i) with the links' flows held fixed, the generator dispatch and the
+    objective equal the exact QP of the remaining AC network, and (ii) each
+    link's flow is optimal at the node prices: strictly inside its limit only
+    where the prices at its two ends agree, at a limit only towards the higher
+    price.  Together these are the optimality conditions of the full problem."""
+    base = synth.config("tiny")
+    inst = synth.with_dc_links(base, 3, seed=3, cap=(0.05, 0.2))
+    s = Solver(inst, Options(eps=1e-9, max_iter=400000))
+    r = s.solve()
+    assert r.converged
+    dcl = np.nonzero(inst.line_kind == 1)[0]
+    f = s.canonical_state()["P"][0, dcl, 0].numpy()
+    cap = inst.line_cap[dcl]
+    lmp = s.lmp()[:, 0].numpy()
+    # (i): the links become fixed injections (a load of f at the from node, -f at the to node)
+    fixed = base.copy()
+    fixed.load_node = np.r_[base.load_node, inst.line_from[dcl], inst.line_to[dcl]].astype(np.int32)
+    fixed.load_d = np.r_[base.load_d, f[:, None], -f[:, None]]
+    x, obj = _tiny_qp(fixed)
+    assert abs(r.objective - obj) <= 1e-5 * abs(obj)
+    np.testing.assert_allclose(s.dispatch()[:inst.G, 0].numpy(), x, atol=2e-5)
+    # (ii)
+    tol = 1e-4 * np.abs(lmp).max()
+    at_limit = np.abs(f) > cap - 1e-5
+    gap = lmp[inst.line_to[dcl]] - lmp[inst.line_from[dcl]]
+    assert np.all(np.abs(gap[~at_limit]) <= tol)
+    assert np.all(np.sign(f[at_limit]) * gap[at_limit] >= -tol)
+    assert at_limit.any() and (~at_limit).any()
+    assert np.abs(gap[at_limit]).max() > 1.0  # a binding link separates the prices
+
+
 def _ptdf(N, frm, to, sus):
     Bm = np.zeros((N, N))
     for f, t, b in zip(frm, to, sus):

@@ -119,6 +119,43 @@ def test_line_prox_outage_and_zero_capacity():
     torch.testing.assert_close(th2, 0.5 * (xi1 + xi2), rtol=0, atol=1e-15)
 
 
+def test_dc_link_prox_brute_force():
+    """HVDC link (Section 2.1): the prox of I{p1 + p2 = 0} + I{|p2| <= c} with
+    no phase relation, against golden-section minimisation of the 1-D
+    objective rho_p/2 ((-P - z1)^2 + (P - z2)^2) over [-c, c]; the phases
+    keep their targets whatever the susceptance."""
+    rng = np.random.default_rng(11)
+    n = 1000
+    z1, z2 = rng.normal(0, 2, n), rng.normal(0, 2, n)
+    xi1, xi2 = rng.normal(0, 0.5, n), rng.normal(0, 0.5, n)
+    s = rng.uniform(0.5, 20, n)
+    c = rng.uniform(0.05, 3, n)
+    rp, rt = rng.uniform(0.1, 10, n), rng.uniform(0.1, 10, n)
+    P = golden_min(lambda x: 0.5 * rp * ((-x - z1) ** 2 + (x - z2) ** 2), -c, c)
+    T = lambda a: torch.tensor(a)
+    dc = torch.ones(n, dtype=torch.bool)
+    p1, p2, th1, th2 = [v.numpy() for v in prox_line(T(z1), T(z2), T(xi1), T(xi2), T(s), T(c),
+                                                     T(rp), T(rt), dc)]
+    np.testing.assert_allclose(p2, P, atol=2e-6)
+    assert np.array_equal(p1, -p2)
+    assert np.array_equal(th1, xi1) and np.array_equal(th2, xi2)
+    clipped = np.abs(np.abs(p2) - c) < 1e-12
+    assert 0.1 < clipped.mean() < 0.9
+    # the susceptance plays no part; an outaged link (c = 0) carries nothing
+    q = prox_line(T(z1), T(z2), T(xi1), T(xi2), T(2 * s + 1), T(c), T(rp), T(rt), dc)
+    assert np.array_equal(q[1].numpy(), p2)
+    q = prox_line(T(z1), T(z2), T(xi1), T(xi2), T(0 * s), T(0 * c), T(rp), T(rt), dc)
+    assert np.all(q[1].numpy() == 0) and np.array_equal(q[2].numpy(), xi1)
+    # mixed masks select per element
+    mix = torch.tensor(rng.random(n) < 0.5)
+    m = prox_line(T(z1), T(z2), T(xi1), T(xi2), T(s), T(c), T(rp), T(rt), mix)
+    ac = prox_line(T(z1), T(z2), T(xi1), T(xi2), T(s), T(c), T(rp), T(rt))
+    for a, b, d in zip(m, ac, (p1, p2, th1, th2)):
+        an = a.numpy()
+        assert np.array_equal(an[mix.numpy()], d[mix.numpy()])
+        assert np.array_equal(an[~mix.numpy()], b.numpy()[~mix.numpy()])
+
+
 # ---- time-coupled devices ------------------------------------------------
 
 def _ramp_exact(c2, c1, pmin, pmax, R, rho_hat, X):
