@@ -97,8 +97,18 @@ void opf_default_options(opf_options* opt);
  * relation between its terminals, so its susceptance is ignored.  Its prox
  * takes the clipped midpoint (z2 - z1)/2 of the two power targets as the
  * flow and leaves both phases at their targets; an outaged DC link carries
- * no power.  The adjoint (opf_tape_forward, opf_adjoint) rejects networks
- * with DC links. */
+ * no power.
+ * General per-contingency line parameters (optional, Section 2.3: in
+ * contingency k the lines may take parameters x_kl other than the base ones):
+ * entry i gives line chg_line[i] the susceptance chg_sus[i] and capacity
+ * chg_cap[i] in contingency chg_k[i] (1..K).  sus = 0 takes an AC line out
+ * (no power, both phases free: a second outage of an N-k contingency); sus > 0
+ * with any cap >= 0 models emergency ratings or switched series devices; for a
+ * DC link only the capacity applies.  A (contingency, line) pair appears at
+ * most once and never repeats that contingency's outage[] line.  n_chg = 0
+ * (the arrays may be NULL): the N-1 outages only.
+ * The adjoint (opf_tape_forward, opf_adjoint) rejects networks with DC links
+ * or changes. */
 typedef struct {
   int32_t N, T, K;
   int32_t L;
@@ -120,6 +130,9 @@ typedef struct {
   const int32_t* bat_node;
   const double *bat_P, *bat_dur, *bat_eta, *bat_alpha;
   const int32_t* line_kind;               /* L entries of 0 or 1, or NULL    */
+  int32_t n_chg;                          /* per-contingency changes         */
+  const int32_t *chg_k, *chg_line;
+  const double *chg_sus, *chg_cap;
 } opf_network;
 
 /* Residual record of one iteration (Section 3.3).  Norms are 2-norms over
@@ -268,7 +281,9 @@ opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, op
  * is the half phase difference of each contingency's outaged line; Hd
  * ([T][chunk][Ldc][w], the chunked layout over the Ldc DC links in line
  * order) holds the half phase difference (theta1 - theta2)/2 of every DC
- * link, whose Tm is the mean phase as for AC lines; device
+ * link, whose Tm is the mean phase as for AC lines; Tz ([T][Zc]) that of the
+ * Zc lines taken out by changes (sus = 0), in the order of the change list;
+ * device
  * arrays pnc, thnc, vbar (contingency mean of the phase duals) are
  * [G+D+B][T].  Element types: state_dtype for all but V1, V2 (dual_dtype).
  * Synchronises. */
@@ -279,6 +294,8 @@ typedef struct {
   size_t P, Tm, V1, V2, Td, U, W, TB, pnc, thnc, vbar;
   int32_t Ldc;            /* DC links */
   size_t Hd;
+  int32_t Zc;             /* lines taken out by changes */
+  size_t Tz;
 } opf_layout;
 opf_status opf_state_layout(opf_ctx* ctx, int32_t instance, opf_layout* out);
 

@@ -111,6 +111,18 @@ class Network:
             if o >= 0:
                 alive[k, o] = 0.0
         self.alive = alive
+        # general contingency parameters (Section 2.3: contingency k may set
+        # any line's parameters x_kl); an entry overrides the base values
+        ck = getattr(inst, "chg_k", None)
+        self.chg = torch.zeros(self.Kp, self.L, dtype=torch.bool)
+        self.chg_sus = torch.zeros(self.Kp, self.L, dtype=DT)
+        self.chg_cap = torch.zeros(self.Kp, self.L, dtype=DT)
+        if ck is not None:
+            for k, l, b, u in zip(np.asarray(ck), np.asarray(inst.chg_line),
+                                  np.asarray(inst.chg_sus, float), np.asarray(inst.chg_cap, float)):
+                self.chg[int(k), int(l)] = True
+                self.chg_sus[int(k), int(l)] = float(b)
+                self.chg_cap[int(k), int(l)] = float(u)
         self.gen_c2, self.gen_c1 = _t(inst.gen_c2), _t(inst.gen_c1)
         self.gen_pmin = _t(inst.gen_pmin)
         self.gen_pmax = _t(inst.gen_pmax) if gen_pmax is None else gen_pmax
@@ -128,6 +140,14 @@ class Network:
         """Sum over the terminals of each node: (Kp, J, T) -> (Kp, N, T)."""
         out = torch.zeros(x.shape[0], self.N, x.shape[2], dtype=x.dtype)
         return out.index_add(1, self.term_node, x)
+
+    def line_params(self):
+        """Susceptance and capacity of every line in every contingency, [K+1][L]:
+        the base values, zeroed for the N-1 outage of each contingency, with
+        the listed per-contingency changes in place (Section 2.3)."""
+        s = torch.where(self.chg, self.chg_sus, self.sus[None, :] * self.alive)
+        c = torch.where(self.chg, self.chg_cap, self.cap[None, :] * self.alive)
+        return s, c
 
     def avg(self, x):
         """xbar_j = (1/|n|) sum_{j' in n} x_j', returned per terminal."""
@@ -375,8 +395,8 @@ class Solver:
         # step 1: contingency prox on the lines, per contingency k
         x = ptil - u
         y = thbar - v
-        s = net.sus[None, :, None] * net.alive[:, :, None]
-        c = net.cap[None, :, None] * net.alive[:, :, None]
+        s, c = net.line_params()
+        s, c = s[:, :, None], c[:, :, None]
         p1, p2, th1, th2 = prox_line(x[:, :L], x[:, L:2 * L], y[:, :L], y[:, L:2 * L],
                                      s, c, rp, rt, net.dc[None, :, None].expand_as(s))
 

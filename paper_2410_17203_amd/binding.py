@@ -60,6 +60,8 @@ class Network(Structure):
         ("bat_P", POINTER(c_double)), ("bat_dur", POINTER(c_double)),
         ("bat_eta", POINTER(c_double)), ("bat_alpha", POINTER(c_double)),
         ("line_kind", POINTER(c_int32)),
+        ("n_chg", c_int32), ("chg_k", POINTER(c_int32)), ("chg_line", POINTER(c_int32)),
+        ("chg_sus", POINTER(c_double)), ("chg_cap", POINTER(c_double)),
     ]
 
 
@@ -89,7 +91,7 @@ class Layout(Structure):
                 ("dual_dtype", c_int32), ("chunk", c_int32),
                 *[(n, c_size_t) for n in ["P", "Tm", "V1", "V2", "Td", "U", "W", "TB", "pnc",
                                           "thnc", "vbar"]],
-                ("Ldc", c_int32), ("Hd", c_size_t)]
+                ("Ldc", c_int32), ("Hd", c_size_t), ("Zc", c_int32), ("Tz", c_size_t)]
 
 
 class OpfError(RuntimeError):
@@ -201,6 +203,13 @@ class NetworkArrays:
         kind = getattr(inst, "line_kind", None)
         if kind is not None:
             n.line_kind = p(kind, i32, c_int32)
+        ck = getattr(inst, "chg_k", None)
+        if ck is not None and len(ck):
+            n.n_chg = len(ck)
+            n.chg_k = p(ck, i32, c_int32)
+            n.chg_line = p(inst.chg_line, i32, c_int32)
+            n.chg_sus = p(inst.chg_sus, f64, c_double)
+            n.chg_cap = p(inst.chg_cap, f64, c_double)
         self.net = n
 
 
@@ -317,6 +326,7 @@ class Solver:
         the next iteration.  Line and node arrays: a list with one [T, count,
         w] tensor per chunk of contingencies (layout()['chunk'] wide, the last one
         narrower); Hd (DC links) likewise over layout()['Ldc'] links; Td [T, Kpp];
+        Tz [T, Zc] (lines taken out by changes);
         device arrays [Jnc, T]."""
         torch = self.torch
         lay = self.layout(instance)
@@ -326,8 +336,8 @@ class Solver:
         T, L, N, Kpp, J = lay["T"], lay["L"], lay["N"], lay["Kpp"], lay["Jnc"]
         esize = torch.empty((), dtype=dtype).element_size()
         off = lay[name] // esize
-        if name in ("Td", "pnc", "thnc", "vbar"):
-            shape = (T, Kpp) if name == "Td" else (J, T)
+        if name in ("Td", "Tz", "pnc", "thnc", "vbar"):
+            shape = {"Td": (T, Kpp), "Tz": (T, lay["Zc"])}.get(name, (J, T))
             n = int(np.prod(shape))
             return self.ws[lay[name]:lay[name] + n * esize].view(dtype).view(shape)
         count = {"P": L, "Tm": L, "V1": L, "V2": L, "Hd": lay["Ldc"]}.get(name, N)

@@ -104,8 +104,8 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
     const R s = R(tp.sus[l]), cap = R(tp.cap[l]);
     LineOut<R, VEC> o;
     line_prox<R, R, VEC>(P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx, to_end ? Bx : Bo,
-                         to_end ? Bo : Bx, ok, l, td_old, false, VR{}, k0, tp.Kp, s, cap, rp, rt,
-                         sv, o);  // networks with DC links are rejected by the tape
+                         to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, s, cap, rp, rt, sv, o);
+    // (networks of the general line model are rejected by the tape)
     NodeAdj<R, VEC> far;
     node_adj<R, VEC>(a, oo, m, t, k0, far);
     const VR Pb = *reinterpret_cast<const VR*>(a.out.P + ol);

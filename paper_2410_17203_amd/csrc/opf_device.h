@@ -515,10 +515,9 @@ __device__ inline R gen_target(R X, R c1, R c2, R rho_hat) {
 
 // Step 1 for one line and one 16-byte vector of contingencies (Section 4.2,
 // DC line prox with the per-contingency susceptance and capacity of the N-1
-// model, or the HVDC link prox when dc: Hd then holds the link's old half
-// phase differences), preceded by the deferred scaled-price update
-// v += theta - thetabar of the previous iteration and the pending penalty
-// rescale.  Both end nodes of a line call this with identical inputs.
+// model), preceded by the deferred scaled-price update v += theta - thetabar
+// of the previous iteration and the pending penalty rescale.  Both end
+// nodes of a line call this with identical inputs.
 template <typename R, int VEC>
 struct LineOut {
   R p[VEC], tm[VEC], v1[VEC], v2[VEC], half[VEC];
@@ -531,9 +530,8 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
                                           const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
                                           const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
                                           const Vec<int32_t, VEC>& ok, int l, const R* td_old,
-                                          bool dc, const Vec<R, VEC>& Hd, int k0, int Kp, R s,
-                                          R cap, R rp, R rt, R sv, LineOut<R, VEC>& o) {
-  if (dc) s = R(1);  // a DC link has no susceptance; keep the unused weights finite
+                                          int k0, int Kp, R s, R cap, R rp, R rt, R sv,
+                                          LineOut<R, VEC>& o) {
   const R inv2s = R(0.5) / s;
   const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;  // 2 rho_p + rho_th / (2 s^2)
   const R ca = rp / den;                                // weight of z2 - z1
@@ -541,7 +539,7 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
     const bool outg = ok.x[e] == l;
-    const R half = dc ? Hd.x[e] : (outg ? td_old[e] : P.x[e] * inv2s);
+    const R half = outg ? td_old[e] : P.x[e] * inv2s;
     const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
     R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
     R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
@@ -553,13 +551,106 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
     if (outg) {
       u = pn = R(0);
       hn = R(0.5) * (xi1 - xi2);
-    } else if (dc) {  // HVDC link: flow at the clipped midpoint, phases at their targets
-      u = R(0.5) * (z2 - z1);
-      pn = clampv(u, -cap, cap);
-      hn = R(0.5) * (xi1 - xi2);
     } else {
       u = ca * (z2 - z1) + cb * (xi1 - xi2);
       pn = clampv(u, -cap, cap);
+      hn = pn * inv2s;
+    }
+    if (k0 + e >= Kp) pn = tm = v1 = v2 = hn = R(0);
+    o.p[e] = pn;
+    o.tm[e] = tm;
+    o.v1[e] = v1;
+    o.v2[e] = v2;
+    o.half[e] = hn;
+    o.u[e] = u;
+  }
+}
+
+// General line model: the parameters of one line in each contingency of a
+// 16-byte vector.  mode 0: AC line in service with susceptance s and
+// capacity cap; 1: out of service (no power, both phases at their targets;
+// the N-1 outage, or a change with zero susceptance); 2: HVDC link (Section
+// 2.1: lossless transfer within cap, no phase relation).  hold: the stored
+// half phase difference where it is not P/(2s) (modes 1 and 2); z: index of
+// a change that takes the line out, whose half difference lives in Tz.
+template <typename R, int VEC>
+struct LinePar {
+  R s[VEC], cap[VEC], hold[VEC];
+  int mode[VEC];
+  int z[VEC];
+};
+
+// Base parameters, the N-1 outage (ok), and the line's changes (CSR entries
+// ordered by contingency) for contingencies k0 .. k0+VEC-1.  dci >= 0 marks
+// a DC link (Hd: its stored half differences; a change sets its capacity).
+template <typename R, int VEC>
+__device__ inline void line_params(const Topo& tp, int l, int k0, const Vec<int32_t, VEC>& ok,
+                                   int dci, const Vec<R, VEC>& Hd, const R* td_old,
+                                   const R* tz_old, LinePar<R, VEC>& q) {
+  const R s = R(tp.sus[l]), cap = R(tp.cap[l]);
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const bool outg = ok.x[e] == l;
+    q.s[e] = s;
+    q.cap[e] = cap;
+    q.z[e] = -1;
+    q.mode[e] = outg ? 1 : (dci >= 0 ? 2 : 0);
+    q.hold[e] = dci >= 0 ? Hd.x[e] : (outg ? td_old[e] : R(0));
+  }
+  const int c1 = tp.chg_ptr[l + 1];
+  for (int c = tp.chg_ptr[l]; c < c1; ++c) {
+    const LineChg ch = tp.chg[c];
+    if (ch.k >= k0 + VEC) break;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      if (ch.k != k0 + e) continue;
+      if (dci >= 0) {
+        q.cap[e] = R(ch.cap);
+      } else if (ch.z >= 0) {
+        q.mode[e] = 1;
+        q.z[e] = ch.z;
+        q.hold[e] = tz_old[ch.z];
+      } else {
+        q.s[e] = R(ch.sus);
+        q.cap[e] = R(ch.cap);
+      }
+    }
+  }
+}
+
+// line_prox with per-contingency parameters (the general line model).
+template <typename R, typename VT, int VEC>
+__device__ __forceinline__ void line_prox_gen(const Vec<R, VEC>& P, const Vec<R, VEC>& Tm,
+                                              const Vec<VT, VEC>& V1, const Vec<VT, VEC>& V2,
+                                              const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
+                                              const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
+                                              const LinePar<R, VEC>& q, int k0, int Kp, R rp,
+                                              R rt, R sv, LineOut<R, VEC>& o) {
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const int mode = q.mode[e];
+    const R inv2s = R(0.5) / (mode == 0 ? q.s[e] : R(1));
+    const R half = mode == 0 ? P.x[e] * inv2s : q.hold[e];
+    const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
+    R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
+    R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
+    const R z1 = -P.x[e] - Wf.x[e];
+    const R z2 = P.x[e] - Wh.x[e];
+    const R xi1 = Bf.x[e] - v1, xi2 = Bh.x[e] - v2;
+    R tm = R(0.5) * (xi1 + xi2);
+    R pn, hn, u;
+    if (mode == 1) {
+      u = pn = R(0);
+      hn = R(0.5) * (xi1 - xi2);
+    } else if (mode == 2) {  // HVDC link: flow at the clipped midpoint, phases at their targets
+      u = R(0.5) * (z2 - z1);
+      pn = clampv(u, -q.cap[e], q.cap[e]);
+      hn = R(0.5) * (xi1 - xi2);
+    } else {
+      const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;
+      const R ca = rp / den, cb = rt * inv2s / den;
+      u = ca * (z2 - z1) + cb * (xi1 - xi2);
+      pn = clampv(u, -q.cap[e], q.cap[e]);
       hn = pn * inv2s;
     }
     if (k0 + e >= Kp) pn = tm = v1 = v2 = hn = R(0);

@@ -44,7 +44,7 @@ struct Layout {
 };
 
 struct BufOffsets {
-  size_t P, Tm, V1, V2, Td, Hd, U, W, TB;
+  size_t P, Tm, V1, V2, Td, Hd, Tz, U, W, TB;
 };
 struct StateOffsets {
   BufOffsets buf[2];
@@ -61,6 +61,7 @@ struct Timed {
 struct Inst {
   int N = 0, T = 0, K = 0, Kp = 0, Kpp = 0, L = 0, G = 0, D = 0, B = 0, Jnc = 0, nR = 0;
   int Ldc = 0;  // DC links
+  int n_chg = 0, Zc = 0;  // per-contingency changes; those that take a line out
   double eps_eff = 0.0, rms_norm = 1.0;
   Topo topo{};
   Geom geom64{}, geom32{};
@@ -73,11 +74,12 @@ struct Inst {
 };
 
 // Offsets of everything one instance holds in the workspace.
-// Snapshot of the iterate of one precision: 16 arrays (line P, Tm, V1, V2,
+// Snapshot of the iterate of one precision: 17 arrays (line P, Tm, V1, V2,
 // outaged half difference, node U, W, thetabar, the two node means, device
 // power/phase/phase dual, ramp and battery inner states, DC link half
-// differences), packed.
-constexpr int kSnapArrays = 16;
+// differences, half differences of lines taken out by changes), packed.
+constexpr int kSnapArrays = 17;
+static_assert(kSnapArrays <= kMaxCopy, "snapshot copy list");
 struct SnapLayout {
   size_t off[kSnapArrays];
   size_t bytes[kSnapArrays];
@@ -108,7 +110,7 @@ struct InstPlan {
       nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
       bat_eta, bat_alpha;
   size_t part_sweep, part_nc;
-  size_t clus_n0, tl_ptr, tl, tcsr, line_dc;
+  size_t clus_n0, tl_ptr, tl, tcsr, line_dc, chg_ptr, chg;
   StateOffsets o64{}, o32{};
 };
 
@@ -222,6 +224,28 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
       seen[o] = 1;
     }
   }
+  if (n->n_chg < 0) return fail(c, OPF_E_INVALID, "n_chg must be >= 0");
+  if (n->n_chg > 0 && (!n->chg_k || !n->chg_line || !n->chg_sus || !n->chg_cap))
+    return fail(c, OPF_E_INVALID, "NULL array for a non-empty change list");
+  {
+    std::vector<std::pair<int, int>> pairs;
+    pairs.reserve(size_t(n->n_chg));
+    for (int i = 0; i < n->n_chg; ++i) {
+      const int k = n->chg_k[i], l = n->chg_line[i];
+      if (k < 1 || k > n->K) return fail(c, OPF_E_INVALID, "change contingency out of range (1..K)");
+      if (l < 0 || l >= n->L) return fail(c, OPF_E_INVALID, "change line index out of range");
+      if (n->outage[k - 1] == l)
+        return fail(c, OPF_E_INVALID, "a change repeats its contingency's outage line");
+      const bool dc = n->line_kind && n->line_kind[l] == 1;
+      if (!(n->chg_cap[i] >= 0.0) || !finite(n->chg_cap[i]) ||
+          (!dc && (!(n->chg_sus[i] >= 0.0) || !finite(n->chg_sus[i]))))
+        return fail(c, OPF_E_INVALID, "a change needs finite sus >= 0 and cap >= 0");
+      pairs.emplace_back(k, l);
+    }
+    std::sort(pairs.begin(), pairs.end());
+    if (std::adjacent_find(pairs.begin(), pairs.end()) != pairs.end())
+      return fail(c, OPF_E_INVALID, "a (contingency, line) pair is changed twice");
+  }
   for (int g = 0; g < n->G; ++g) {
     if (!node_ok(n->gen_node[g])) return fail(c, OPF_E_INVALID, "generator node out of range");
     deg[n->gen_node[g]]++;
@@ -269,6 +293,13 @@ void set_sizes(Inst& s, const opf_network* n) {
   s.Ldc = 0;
   if (n->line_kind)
     for (int l = 0; l < n->L; ++l) s.Ldc += n->line_kind[l] == 1;
+  s.n_chg = n->n_chg;
+  s.Zc = 0;
+  for (int i = 0; i < n->n_chg; ++i) {
+    const int l = n->chg_line[i];
+    const bool dc = n->line_kind && n->line_kind[l] == 1;
+    if (!dc && n->chg_sus[i] == 0.0) s.Zc++;
+  }
   s.nR = 0;
   if (n->T > 1)
     for (int g = 0; g < n->G; ++g)
@@ -325,6 +356,7 @@ void state_offsets(const Inst& s, Layout& lay, StateOffsets& o) {
     b.V2 = lay.take(line * sizeof(VT));
     b.Td = lay.take(size_t(s.T) * s.Kpp * sizeof(R));
     b.Hd = lay.take(size_t(s.Ldc) * s.T * s.Kpp * sizeof(R));
+    b.Tz = lay.take(size_t(s.Zc) * s.T * sizeof(R));
     b.U = lay.take(node * sizeof(R));
     b.W = lay.take(node * sizeof(R));
     b.TB = lay.take(node * sizeof(R));
@@ -352,6 +384,7 @@ State<R, VT> state_ptrs(char* ws, const StateOffsets& o) {
     d.V2 = reinterpret_cast<VT*>(ws + b.V2);
     d.Td = reinterpret_cast<R*>(ws + b.Td);
     d.Hd = reinterpret_cast<R*>(ws + b.Hd);
+    d.Tz = reinterpret_cast<R*>(ws + b.Tz);
     d.U = reinterpret_cast<R*>(ws + b.U);
     d.W = reinterpret_cast<R*>(ws + b.W);
     d.TB = reinterpret_cast<R*>(ws + b.TB);
@@ -385,6 +418,8 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
   p.tl = L.take(2 * Li * 16);
   p.tcsr = L.take(2 * Li * 4);
   p.line_dc = L.take(Li * 4);
+  p.chg_ptr = L.take((Li + 1) * 4);
+  p.chg = L.take(size_t(s.n_chg) * sizeof(LineChg));
   p.nc_node = L.take(size_t(s.Jnc) * 4);
   p.ramp_idx = L.take(Gi * 4);
   p.gen_c2 = L.take(Gi * 8);
@@ -636,8 +671,8 @@ opf_status refresh_geometry(opf_ctx* c) {
     t.dev_prefix = c->d_dev_prefix;
     t.grp_prefix = grp;
     t.n_inst = n;
-    t.any_dc = 0;
-    for (const Inst& x : c->inst) t.any_dc |= x.Ldc > 0 ? 1 : 0;
+    t.any_gen = 0;
+    for (const Inst& x : c->inst) t.any_gen |= (x.Ldc > 0 || x.n_chg > 0) ? 1 : 0;
     t.total_dev = dev[n];
     t.total_grps = total_grps;
     int nb = std::max(8, round8(std::min<int64_t>(total_grps, kMaxSweepBlocks)));
@@ -823,6 +858,29 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
         sus[l] = 1.0;
       }
   }
+  // per-contingency changes: CSR by line, entries by contingency; changes
+  // that take an AC line out are numbered (z) in input order
+  std::vector<int32_t> chg_ptr(L + 1, 0);
+  std::vector<LineChg> chg(size_t(s.n_chg));
+  {
+    std::vector<int32_t> zid(size_t(s.n_chg), -1);
+    int z = 0;
+    for (int i = 0; i < s.n_chg; ++i) {
+      const int l = n->chg_line[i];
+      chg_ptr[l + 1]++;
+      if (line_dc[l] < 0 && n->chg_sus[i] == 0.0) zid[i] = z++;
+    }
+    for (int l = 0; l < L; ++l) chg_ptr[l + 1] += chg_ptr[l];
+    std::vector<int32_t> order(size_t(s.n_chg));
+    for (int i = 0; i < s.n_chg; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return std::make_pair(n->chg_line[a], n->chg_k[a]) < std::make_pair(n->chg_line[b], n->chg_k[b]);
+    });
+    for (int q = 0; q < s.n_chg; ++q) {
+      const int i = order[q];
+      chg[q] = LineChg{n->chg_k[i], zid[i], n->chg_sus[i], n->chg_cap[i]};
+    }
+  }
   double lsum = 0.0;
   for (size_t i = 0; i < size_t(D) * T; ++i) lsum += n->load_d[i] * n->load_d[i];
   const double load_rms = (size_t(D) * T > 0) ? std::sqrt(lsum / double(size_t(D) * T)) : 1.0;
@@ -835,6 +893,8 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   HIP_TRY(c, up(p.line_to, n->line_to, size_t(L) * 4));
   HIP_TRY(c, up(p.sus, sus.data(), size_t(L) * 8));
   HIP_TRY(c, up(p.line_dc, line_dc.data(), size_t(L) * 4));
+  HIP_TRY(c, up(p.chg_ptr, chg_ptr.data(), size_t(L + 1) * 4));
+  HIP_TRY(c, up(p.chg, chg.data(), chg.size() * sizeof(LineChg)));
   HIP_TRY(c, up(p.cap, n->line_cap, size_t(L) * 8));
   HIP_TRY(c, up(p.outage_k, outage_k.data(), size_t(Kpp) * 4));
   HIP_TRY(c, up(p.node_lptr, lptr.data(), size_t(N + 1) * 4));
@@ -882,6 +942,10 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   tp.tcsr = reinterpret_cast<const int32_t*>(ws + p.tcsr);
   tp.Ldc = s.Ldc;
   tp.line_dc = reinterpret_cast<const int32_t*>(ws + p.line_dc);  // all -1 without DC links
+  tp.n_chg = s.n_chg;
+  tp.Zc = s.Zc;
+  tp.chg_ptr = reinterpret_cast<const int32_t*>(ws + p.chg_ptr);
+  tp.chg = reinterpret_cast<const LineChg*>(ws + p.chg);
   tp.nc_node = reinterpret_cast<const int32_t*>(ws + p.nc_node);
   tp.ramp_idx = reinterpret_cast<const int32_t*>(ws + p.ramp_idx);
   tp.gen_c2 = reinterpret_cast<const double*>(ws + p.gen_c2);
@@ -1035,7 +1099,7 @@ SnapLayout snap_layout(const Inst& s, int precision) {
       line, line, line, line, size_t(s.T) * s.Kpp * S, node, node, node,
       size_t(s.N) * s.T * S, size_t(s.N) * s.T * S, size_t(s.Jnc) * s.T * S,
       size_t(s.Jnc) * s.T * S, size_t(s.Jnc) * s.T * S, 4 * size_t(s.nR) * s.T * S,
-      6 * size_t(s.B) * s.T * S, size_t(s.Ldc) * s.T * s.Kpp * S};
+      6 * size_t(s.B) * s.T * S, size_t(s.Ldc) * s.T * s.Kpp * S, size_t(s.Zc) * s.T * S};
   SnapLayout sl{};
   Layout L;
   for (int i = 0; i < kSnapArrays; ++i) {
@@ -1093,7 +1157,8 @@ void state_arrays(const State<R, R>& st, int cur, char* (&out)[kSnapArrays]) {
       reinterpret_cast<char*>(st.avgW), reinterpret_cast<char*>(st.avgTB),
       reinterpret_cast<char*>(st.pnc), reinterpret_cast<char*>(st.thnc),
       reinterpret_cast<char*>(st.vbar), reinterpret_cast<char*>(st.ramp_st),
-      reinterpret_cast<char*>(st.bat_st), reinterpret_cast<char*>(b.Hd)};
+      reinterpret_cast<char*>(st.bat_st), reinterpret_cast<char*>(b.Hd),
+      reinterpret_cast<char*>(b.Tz)};
   for (int i = 0; i < kSnapArrays; ++i) out[i] = a[i];
 }
 
@@ -1141,7 +1206,8 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
   a.A.V1 = sp(2);
   a.A.V2 = sp(3);
   a.A.Td = sp(4);
-  a.A.Hd = nullptr;  // no DC links on a tape
+  a.A.Hd = nullptr;  // no DC links or changes on a tape
+  a.A.Tz = nullptr;
   a.A.U = sp(5);
   a.A.W = sp(6);
   a.A.TB = sp(7);
@@ -1197,6 +1263,8 @@ opf_status tape_check(opf_ctx* c) {
   if (c->opt.inner_iters > kMaxAdjInner)
     return fail(c, OPF_E_INVALID, "the adjoint supports inner_iters <= 32");
   if (c->inst[0].Ldc > 0) return fail(c, OPF_E_INVALID, "the adjoint does not support DC links");
+  if (c->inst[0].n_chg > 0)
+    return fail(c, OPF_E_INVALID, "the adjoint does not support per-contingency changes");
   return OPF_OK;
 }
 
@@ -1334,7 +1402,7 @@ struct BlobHead {
   int32_t version, precision, N, T, K, L, Jnc, nR, B;
   double rho_p, rho_th;
   double su, sv;  // pending rescale ratios (deferred to the next iteration)
-  int32_t Ldc;
+  int32_t Ldc, n_chg, Zc;
 };
 constexpr size_t kBlobHead = 256;
 static_assert(sizeof(BlobHead) <= kBlobHead, "blob header");
@@ -1774,6 +1842,7 @@ opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
   out->dual_dtype = c->precision == 0 ? OPF_F64 : (c->bf16_duals ? OPF_BF16 : OPF_F32);
   out->chunk = kChunk;
   out->Ldc = x.Ldc;
+  out->Zc = x.Zc;
   auto off = [&](const void* p) { return size_t(static_cast<const char*>(p) - c->ws); };
   auto fill = [&](const auto& st) {
     const auto& b = st.buf[cur];
@@ -1783,6 +1852,7 @@ opf_status opf_state_layout(opf_ctx* c, int32_t instance, opf_layout* out) {
     out->V2 = off(b.V2);
     out->Td = off(b.Td);
     out->Hd = off(b.Hd);
+    out->Tz = off(b.Tz);
     out->U = off(b.U);
     out->W = off(b.W);
     out->TB = off(b.TB);
@@ -1829,6 +1899,8 @@ opf_status opf_get_state(opf_ctx* c, void* dst, size_t bytes) {
   hd.nR = x.nR;
   hd.B = x.B;
   hd.Ldc = x.Ldc;
+  hd.n_chg = x.n_chg;
+  hd.Zc = x.Zc;
   hd.rho_p = h.rho_p;
   hd.rho_th = h.rho_th;
   hd.su = h.su;
@@ -1855,7 +1927,8 @@ opf_status opf_set_state(opf_ctx* c, const void* src, size_t bytes) {
   if (std::memcmp(hd.magic, "OPFSTATE", 8) != 0 || hd.version != 1)
     return fail(c, OPF_E_INVALID, "not a state exported by opf_get_state");
   if (hd.N != x.N || hd.T != x.T || hd.K != x.K || hd.L != x.L || hd.Jnc != x.Jnc ||
-      hd.nR != x.nR || hd.B != x.B || hd.Ldc != x.Ldc)
+      hd.nR != x.nR || hd.B != x.B || hd.Ldc != x.Ldc ||
+      hd.n_chg != x.n_chg || hd.Zc != x.Zc)
     return fail(c, OPF_E_INVALID, "state was exported from a network of another shape");
   if (!(hd.precision == 0 ? c->has64 : c->has32))
     return fail(c, OPF_E_INVALID, "state precision is not held by this context");

@@ -18,7 +18,8 @@
 // P / (2 b) for a live line and, for the one outaged line of contingency k,
 // a separate [T][Kpp] array Td.  A DC link has no phase relation, so its
 // half difference is state of its own: Hd [T][chunk][Ldc][w] over the DC
-// links in line order.  Line and node arrays are double-buffered
+// links in line order; so is that of a line taken out by a general
+// per-contingency change: Tz [T][Zc].  Line and node arrays are double-buffered
 // (the sweep reads one buffer and writes the other).
 #pragma once
 
@@ -57,6 +58,14 @@ __host__ __device__ inline size_t ck_off(int t, int i, int k, int count, int Kpp
   const int w = Kpp - c0 < kChunk ? Kpp - c0 : kChunk;
   return (size_t(t) * Kpp + c0) * size_t(count) + size_t(i) * w + (k - c0);
 }
+
+// One general per-contingency parameter change of a line (Section 2.3):
+// contingency k gives the line susceptance sus and capacity cap; z >= 0
+// numbers the changes that take an AC line out (sus = 0).
+struct LineChg {
+  int32_t k, z;
+  double sus, cap;
+};
 
 struct bf16_t {
   uint16_t u;
@@ -119,9 +128,13 @@ struct Topo {
   const int32_t* tl_ptr;      // [Q+1] range of each cluster's lines in tl
   const int4* tl;             // (line, local from node or -1, local to node or -1, far node or -1)
   const int32_t* tcsr;        // parallel to node_lterm: 2 * (index in the cluster's tl) + end
-  // DC links (Ldc = 0: none; the sweeps then run a variant that never reads line_dc)
+  // General line model (the sweeps run a variant that reads these only when
+  // the instance has DC links or per-contingency changes)
   int32_t Ldc;
   const int32_t* line_dc;     // [L] index among the DC links, -1 for an AC line
+  int32_t n_chg, Zc;          // changes; changes that take a line out
+  const int32_t* chg_ptr;     // [L+1] CSR by line, entries ordered by contingency
+  const LineChg* chg;
 };
 
 // Double-buffered part of the iterate.
@@ -133,6 +146,7 @@ struct Buf {
   VT* V2;
   R* Td;      // [T][Kpp]
   R* Hd;      // [T][chunk][Ldc][w]
+  R* Tz;      // [T][Zc]
   R* U;
   R* W;
   R* TB;
@@ -185,7 +199,7 @@ struct BatchTab {
   const int64_t* grp_prefix;  // [n_inst + 1]
   int32_t n_inst;
   int32_t n_sweep_blocks;
-  int32_t any_dc;             // some instance holds DC links
+  int32_t any_gen;            // some instance has DC links or per-contingency changes
   int64_t total_dev;
   int64_t total_grps;
 };
@@ -278,11 +292,12 @@ struct AdjArgs {
   double w_obj;   // weight of the objective in the cotangent
 };
 
-// Copy of up to 16 device arrays in one launch (snapshots of the iterate).
+// Copy of up to 20 device arrays in one launch (snapshots of the iterate).
+constexpr int kMaxCopy = 20;
 struct CopyList {
-  const char* src[16];
-  char* dst[16];
-  size_t bytes[16];
+  const char* src[kMaxCopy];
+  char* dst[kMaxCopy];
+  size_t bytes[kMaxCopy];
   int32_t n;
 };
 

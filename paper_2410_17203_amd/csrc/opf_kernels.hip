@@ -101,8 +101,9 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
 // Steps 1 and 3 for one (period, node) row and one 16-byte vector of
 // contingencies.  acc: FP64 residual partials [sum |n| pbar^2, sum theta
 // tilde^2, sum |n| dpbar^2, sum |n| dthetabar^2, sum over lines of 2 dP^2].
-// DC: the instance may hold DC links (compiled out otherwise).
-template <typename R, typename VT, bool DC>
+// GEN: the general line model (DC links, per-contingency changes); the plain
+// N-1 model otherwise.
+template <typename R, typename VT, bool GEN>
 __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, const Buf<R, VT>& B,
                                  int row, int v, int q0, int q1, bool check, R rp, R rt, R sv,
                                  double (&acc)[5], R& sumw, R& sumb) {
@@ -153,15 +154,24 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       const int l = term[u].x >> 1;
       const bool to_end = term[u].x & 1;  // this node is the line's terminal-2 node
       const size_t ol = ck_off(t, l, k0, tp.L, tp.Kpp);
-      // (a batch runs this variant for every instance, with or without links)
-      const int dci = (DC && tp.line_dc) ? tp.line_dc[l] : -1;
-      const size_t oh = dci >= 0 ? ck_off(t, dci, k0, tp.Ldc, tp.Kpp) : 0;
-      VR Hx{};
-      if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
       LineOut<R, VEC> o;
-      line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo, to_end ? Wo : Wx[u],
-                            to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l, td_old, dci >= 0, Hx,
-                            k0, tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+      int dci = -1;
+      size_t oh = 0;
+      LinePar<R, VEC> lp;
+      if constexpr (GEN) {
+        dci = tp.line_dc[l];
+        oh = dci >= 0 ? ck_off(t, dci, k0, tp.Ldc, tp.Kpp) : 0;
+        VR Hx{};
+        if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
+        line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old, A.Tz + size_t(t) * tp.Zc, lp);
+        line_prox_gen<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo,
+                                  to_end ? Wo : Wx[u], to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], lp,
+                                  k0, tp.Kp, rp, rt, sv, o);
+      } else {
+        line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo,
+                              to_end ? Wo : Wx[u], to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l,
+                              td_old, k0, tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+      }
       if (!to_end) {  // the from node stores the line's new state
         VR Pn, Tn;
         VV V1n, V2n;
@@ -181,11 +191,16 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
         st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
         st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
         st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-        if (dci >= 0) {
-          VR Hn;
+        if constexpr (GEN) {
+          if (dci >= 0) {
+            VR Hn;
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) Hn.x[e] = o.half[e];
-          *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+            for (int e = 0; e < VEC; ++e) Hn.x[e] = o.half[e];
+            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+          }
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (lp.z[e] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[e]] = o.half[e];
         }
       }
 #pragma unroll
@@ -253,7 +268,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
 // of two, at most one wavefront); each lane takes the row's 16-byte vectors
 // q, q + lanes_per_row, ...  The contingency sums of a row are reduced with
 // shuffles inside its lane group (no LDS, no barrier).
-template <typename R, typename VT, bool DC>
+template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a) {
   Ctl* ctl = a.g.ctl;
   if (ctl->done) return;
@@ -279,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT, DC>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, GEN>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
@@ -311,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // registers of the thread that owns the node across the chunks.  Tiles of
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
-template <typename R, typename VT, bool DC>
+template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
@@ -393,14 +408,22 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
         }
         const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
-        const int dci = (DC && tp.line_dc) ? tp.line_dc[l] : -1;
-        const size_t oh =
-            dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC : 0;
-        VR Hx{};
-        if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
         LineOut<R, VEC> o;
-        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, dci >= 0, Hx, k0,
-                              tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+        int dci = -1;
+        size_t oh = 0;
+        LinePar<R, VEC> lp;
+        if constexpr (GEN) {
+          dci = tp.line_dc[l];
+          oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
+                        : 0;
+          VR Hx{};
+          if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
+          line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
+          line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
+        } else {
+          line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
+                                R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+        }
         if (e.y >= 0) {  // the cluster holding the from node stores the line
           VR Pn, Tn;
           VV V1n, V2n;
@@ -420,11 +443,16 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
           st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
           st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-          if (dci >= 0) {
-            VR Hn;
+          if constexpr (GEN) {
+            if (dci >= 0) {
+              VR Hn;
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
-            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+              for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
+              *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+            }
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+              if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
           }
         }
         VR Po, To, Ho;
@@ -734,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
   }
 }
 
-template <typename R, typename VT, bool DC>
+template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
@@ -761,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT, DC>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, GEN>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
@@ -832,10 +860,22 @@ __global__ void __launch_bounds__(kBlock) k_export(KArgs<R, VT> a, int field, do
       return;
     }
     const bool outg = tp.outage_k[k] == l;
-    const int dci = tp.line_dc ? tp.line_dc[l] : -1;
-    const double half = dci >= 0 ? double(C.Hd[ck_off(t, dci, k, tp.Ldc, tp.Kpp)])
-                        : outg   ? double(C.Td[size_t(t) * tp.Kpp + k])
-                                 : P * (0.5 / tp.sus[l]);
+    const int dci = tp.line_dc[l];
+    double half;
+    if (dci >= 0) {
+      half = double(C.Hd[ck_off(t, dci, k, tp.Ldc, tp.Kpp)]);
+    } else if (outg) {
+      half = double(C.Td[size_t(t) * tp.Kpp + k]);
+    } else {
+      double s = tp.sus[l];
+      int z = -1;
+      for (int c = tp.chg_ptr[l]; c < tp.chg_ptr[l + 1]; ++c)
+        if (tp.chg[c].k == k) {
+          s = tp.chg[c].sus;
+          z = tp.chg[c].z;
+        }
+      half = z >= 0 ? double(C.Tz[size_t(t) * tp.Zc + z]) : P * (0.5 / s);
+    }
     const double th1 = double(C.Tm[o]) + half, th2 = double(C.Tm[o]) - half;
     if (field == 1) dst[i] = th1;
     if (field == 2) dst[i] = th2;
@@ -904,14 +944,14 @@ int sweep_resident_blocks() {
 
 template <typename R, typename VT>
 void launch_sweep(const KArgs<R, VT>& a, hipStream_t s) {
-  const bool dc = a.tp.Ldc > 0;
+  const bool gen = a.tp.Ldc > 0 || a.tp.n_chg > 0;
   if (a.g.tile_blocks > 0) {
-    if (dc)
+    if (gen)
       k_sweep_tile<R, VT, true><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
     else
       k_sweep_tile<R, VT, false><<<a.g.tile_blocks, kTileBlock, 0, s>>>(a);
   } else {
-    if (dc)
+    if (gen)
       k_sweep<R, VT, true><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
     else
       k_sweep<R, VT, false><<<a.g.n_sweep_blocks, kBlock, 0, s>>>(a);
@@ -975,6 +1015,7 @@ void launch_widen(const KArgs<float, VT>& a, const KArgs<double, double>& b, hip
     widen(x.V2, y.V2, line, s);
     widen(x.Td, y.Td, int64_t(tp.T) * tp.Kpp, s);
     widen(x.Hd, y.Hd, int64_t(tp.Ldc) * tp.T * tp.Kpp, s);
+    widen(x.Tz, y.Tz, int64_t(tp.T) * tp.Zc, s);
     widen(x.U, y.U, node, s);
     widen(x.W, y.W, node, s);
     widen(x.TB, y.TB, node, s);
@@ -1004,7 +1045,7 @@ void launch_batch_iter_devices(const BatchTab& tab, int max_T, hipStream_t s) {
 
 template <typename R, typename VT>
 void launch_batch_iter_sweep(const BatchTab& tab, hipStream_t s) {
-  if (tab.any_dc)
+  if (tab.any_gen)
     k_sweep_batch<R, VT, true><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
   else
     k_sweep_batch<R, VT, false><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);

@@ -74,6 +74,13 @@ class Instance:
     bat_eta: np.ndarray
     bat_alpha: np.ndarray
     line_kind: Optional[np.ndarray] = None  # [L] 0 = AC line, 1 = DC link; None = all AC
+    # per-contingency line parameters (Section 2.3): contingency chg_k[i] gives
+    # line chg_line[i] susceptance chg_sus[i] and capacity chg_cap[i]
+    # (susceptance 0: the line is out); None = the N-1 outages only
+    chg_k: Optional[np.ndarray] = None
+    chg_line: Optional[np.ndarray] = None
+    chg_sus: Optional[np.ndarray] = None
+    chg_cap: Optional[np.ndarray] = None
     meta: Dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -455,3 +462,62 @@ def with_dc_links(inst: Instance, count: int = 3, seed: int = 0, outage_first: b
         outage=outage,
         line_kind=np.r_[kind0, np.ones(count, np.int32)],
     )
+
+
+def with_contingency_changes(inst: Instance, seed: int = 0, second_outages: int = 2,
+                             rating_changes: int = 6, sus_changes: int = 3) -> Instance:
+    """The same network with general per-contingency line parameters (Section
+    2.3: contingency k may change any line's parameters, not only remove one):
+
+    * `second_outages` contingencies also lose a second line (N-2), chosen so
+      that the grid stays connected;
+    * `rating_changes` (contingency, line) pairs get a post-contingency
+      (emergency) capacity U[1.1, 1.5] times the base one;
+    * `sus_changes` pairs get a susceptance U[0.5, 0.9] times the base one
+      (a switched series device) with the base capacity.
+
+    Pairs are distinct and never the contingency's own N-1 outage."""
+    import dataclasses as _dc
+    rng = np.random.default_rng([seed, 0xC4])
+    K, L, N = int(inst.K), len(inst.line_from), int(inst.N)
+    frm, to = np.asarray(inst.line_from), np.asarray(inst.line_to)
+    outage = np.asarray(inst.outage)
+    used = {(k + 1, int(outage[k])) for k in range(K) if outage[k] >= 0}
+    ks, ls, bs, us = [], [], [], []
+    sus = np.asarray(inst.line_sus, float)
+    cap = np.asarray(inst.line_cap, float)
+
+    def free_pair(k):
+        for _ in range(1000):
+            l = int(rng.integers(0, L))
+            if (k, l) not in used:
+                return l
+        raise RuntimeError("no free (contingency, line) pair")
+
+    if K >= 1 and second_outages > 0:
+        for k in rng.choice(np.arange(1, K + 1), min(second_outages, K), replace=False):
+            k = int(k)
+            for _ in range(1000):
+                l = free_pair(k)
+                keep = np.ones(L, bool)
+                keep[l] = False
+                if outage[k - 1] >= 0:
+                    keep[outage[k - 1]] = False
+                if len(np.unique(_components(N, np.stack([frm[keep], to[keep]], 1)))) == 1:
+                    break
+            else:
+                raise RuntimeError("no second outage keeps the grid connected")
+            used.add((k, l))
+            ks.append(k); ls.append(l); bs.append(0.0); us.append(0.0)
+    for n_pairs, kind in ((rating_changes, "cap"), (sus_changes, "sus")):
+        for _ in range(n_pairs if K >= 1 else 0):
+            k = int(rng.integers(1, K + 1))
+            l = free_pair(k)
+            used.add((k, l))
+            ks.append(k); ls.append(l)
+            if kind == "cap":
+                bs.append(sus[l]); us.append(cap[l] * rng.uniform(1.1, 1.5))
+            else:
+                bs.append(sus[l] * rng.uniform(0.5, 0.9)); us.append(cap[l])
+    return _dc.replace(inst, chg_k=np.asarray(ks, np.int32), chg_line=np.asarray(ls, np.int32),
+                       chg_sus=np.asarray(bs, float), chg_cap=np.asarray(us, float))

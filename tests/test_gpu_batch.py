@@ -38,6 +38,7 @@ def batch_instances():
                                        D=int(0.8 * N), B=max(1, N // 25), T=T, K=K,
                                        seed=900 + i))
     out[2] = synth.with_dc_links(out[2], 3, seed=2)  # DC links beside AC-only instances
+    out[3] = synth.with_contingency_changes(out[3], seed=3)  # per-contingency changes
     return out
 
 

@@ -120,3 +120,35 @@ def test_dc_link_rules_are_enforced():
         assert torch.equal(s.field(f), t.field(f)), f
     s.close()
     t.close()
+
+
+def test_change_rules_are_enforced():
+    """Invalid per-contingency changes are rejected (contingency or line out
+    of range, a pair given twice, a pair repeating its contingency's outage,
+    negative values); the adjoint rejects networks with changes."""
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import OpfError, Solver
+    base = synth.make_instance("chg_rules", N=12, L=17, G=4, D=8, B=1, T=4, K=3, seed=5)
+
+    def with_chg(k, l, b, u):
+        x = base.copy()
+        x.chg_k, x.chg_line = np.array(k, np.int32), np.array(l, np.int32)
+        x.chg_sus, x.chg_cap = np.array(b, float), np.array(u, float)
+        return x
+
+    free = [q for q in range(base.L) if q not in set(base.outage.tolist())]
+    bad = [(with_chg([0], [free[0]], [1.0], [1.0]), "contingency out of range"),
+           (with_chg([4], [free[0]], [1.0], [1.0]), "contingency out of range"),
+           (with_chg([1], [base.L], [1.0], [1.0]), "line index out of range"),
+           (with_chg([1, 1], [free[0], free[0]], [1.0, 2.0], [1.0, 1.0]), "changed twice"),
+           (with_chg([2], [int(base.outage[1])], [1.0], [1.0]), "repeats its contingency"),
+           (with_chg([1], [free[0]], [-1.0], [1.0]), "finite sus"),
+           (with_chg([1], [free[0]], [1.0], [np.nan]), "finite sus")]
+    for inst, msg in bad:
+        with pytest.raises(OpfError, match=msg):
+            Solver(inst, dtype="f64")
+    s = Solver(with_chg([1, 3], [free[0], free[1]], [0.0, 2.0], [0.0, 0.5]), dtype="f64",
+               polish_fp64=0)
+    with pytest.raises(OpfError, match="per-contingency changes"):
+        s.tape_forward(10, 5)
+    s.close()

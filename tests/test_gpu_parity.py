@@ -60,6 +60,25 @@ def make(name):
     if name == "hvdc":  # DC links (Section 2.1), one outaged by contingency 1; two chunks
         base = synth.make_instance("hvdc", N=30, L=60, G=8, D=20, B=3, T=6, K=37, seed=77)
         return synth.with_dc_links(base, 4, seed=5)
+    if name == "changes":  # general per-contingency parameters (Section 2.3), two chunks
+        base = synth.make_instance("chg", N=30, L=60, G=8, D=20, B=3, T=6, K=37, seed=78)
+        return synth.with_contingency_changes(base, seed=6, second_outages=5, rating_changes=40,
+                                              sus_changes=20)
+    if name == "changes_dc":  # changes that also reach DC links
+        base = synth.with_dc_links(
+            synth.make_instance("chgdc", N=30, L=60, G=8, D=20, B=3, T=6, K=9, seed=79), 4, seed=7)
+        inst = synth.with_contingency_changes(base, seed=8, second_outages=3, rating_changes=15,
+                                              sus_changes=8)
+        dcl = np.nonzero(inst.line_kind == 1)[0]
+        # make sure some changes land on DC links: a derating and a disconnection
+        k = inst.chg_k
+        extra = [(int(kk), int(l), 10.0, c) for kk, l, c in [(2, dcl[1], 0.3), (5, dcl[2], 0.0)]
+                 if not np.any((k == kk) & (inst.chg_line == l))]
+        inst.chg_k = np.r_[k, [e[0] for e in extra]].astype(np.int32)
+        inst.chg_line = np.r_[inst.chg_line, [e[1] for e in extra]].astype(np.int32)
+        inst.chg_sus = np.r_[inst.chg_sus, [e[2] for e in extra]]
+        inst.chg_cap = np.r_[inst.chg_cap, [e[3] for e in extra]]
+        return inst
     if name == "tiny_dc":  # binding and free DC links in the tiny grid
         return synth.with_dc_links(synth.config("tiny"), 3, seed=3, cap=(0.05, 0.2))
     if name == "no_batteries_T1":
@@ -106,7 +125,7 @@ def compare_fields(s, ref, tol, skip=()):
 
 
 @pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1",
-                                  "curtailable", "hvdc"])
+                                  "curtailable", "hvdc", "changes", "changes_dc"])
 @pytest.mark.parametrize("tiles", [0, 1])
 def test_fp64_iterates_match_oracle(name, tiles):
     say(f"[parity fp64] {name} tiles={tiles}")
@@ -128,7 +147,7 @@ def test_fp64_iterates_match_oracle(name, tiles):
 
 @pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("name", ["medium", "wide_T", "edge", "no_batteries_T1", "hub",
-                                  "curtailable", "hvdc"])
+                                  "curtailable", "hvdc", "changes", "changes_dc"])
 def test_fp32_iterates_match_oracle(name, tiles):
     """FP32 iterate with the node-row sweep and with the sweep over clusters
     of consecutive nodes (several chunks of contingencies, a ragged last

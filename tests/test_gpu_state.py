@@ -155,3 +155,38 @@ def test_dc_link_state_view_and_continuation():
         c.set_state(blob)
     for x in (a, b, c):
         x.close()
+
+
+def test_change_state_view_and_continuation():
+    """With lines taken out by per-contingency changes the iterate holds their
+    half phase differences (view 'Tz', in the order of the change list), and
+    an exported state carries them."""
+    from paper_2410_17203_amd.binding import Solver
+    say("[state] per-contingency changes")
+    inst = synth.with_contingency_changes(small(), seed=3, second_outages=3, rating_changes=5,
+                                          sus_changes=4)
+    out = inst.chg_sus == 0
+    opts = dict(adapt_every=0, polish_fp64=0)
+    a = Solver(inst, dtype="f64", **opts)
+    a.iterate(30)
+    lay = a.layout()
+    assert lay["Zc"] == int(out.sum()) == 3
+    tz = a.view("Tz").double().cpu()                                   # [T, Zc]
+    th1, th2 = a.field("TH1"), a.field("TH2")                          # [K+1, L, T]
+    k, l = inst.chg_k[out], inst.chg_line[out]
+    half = 0.5 * (th1 - th2)[k, l, :]                                  # [Zc, T]
+    torch.testing.assert_close(tz.T, half, rtol=0, atol=1e-15)
+    assert float(half.abs().max()) > 0
+    assert torch.all(a.field("P")[k, l, :] == 0)
+    blob = a.get_state()
+    a.iterate(25)
+    b = Solver(inst, dtype="f64", **opts)
+    b.set_state(blob)
+    b.iterate(25)
+    for f in ["P", "TH1", "TH2", "V1", "U", "THBAR", "PNC"]:
+        assert torch.equal(a.field(f), b.field(f)), f
+    c = Solver(small(), dtype="f64", **opts)
+    with pytest.raises(Exception, match="another shape"):
+        c.set_state(blob)
+    for x in (a, b, c):
+        x.close()

@@ -200,6 +200,173 @@ def test_dc_links_satisfy_optimality():
     assert np.abs(gap[at_limit]).max() > 1.0  # a binding link separates the prices
 
 
+def _line_params_by_hand(inst):
+    """Per-(k, l) susceptance and capacity written out from the instance."""
+    K, L = int(inst.K), len(inst.line_from)
+    sus = np.tile(np.asarray(inst.line_sus, float), (K + 1, 1))
+    cap = np.tile(np.asarray(inst.line_cap, float), (K + 1, 1))
+    for k in range(1, K + 1):
+        o = int(inst.outage[k - 1])
+        if o >= 0:
+            sus[k, o] = cap[k, o] = 0.0
+    if getattr(inst, "chg_k", None) is not None:
+        for k, l, b, u in zip(inst.chg_k, inst.chg_line, inst.chg_sus, inst.chg_cap):
+            sus[k, l], cap[k, l] = b, u
+    return sus, cap
+
+
+def _coupled_qp(inst):
+    """The contingency-constrained problem of Section 2.3 at T = 1 as a QP in
+    the generator outputs and every contingency's node phases: the lines of
+    contingency k carry sus_kl (theta_f - theta_t) within cap_kl, every node
+    balances in every contingency, and the generators, loads and batteries
+    keep one power and one phase schedule across contingencies, so a node
+    hosting any of them has the same phase in every contingency.  Solved with
+    scipy's SLSQP after dropping linearly dependent equality rows."""
+    from scipy.linalg import qr
+    from scipy.optimize import minimize
+    N, G, L, K = int(inst.N), len(inst.gen_node), len(inst.line_from), int(inst.K)
+    sus, cap = _line_params_by_hand(inst)
+    frm, to = np.asarray(inst.line_from), np.asarray(inst.line_to)
+    dev = np.zeros(N, bool)
+    dev[inst.gen_node] = dev[inst.load_node] = True
+    if len(inst.bat_node):
+        dev[inst.bat_node] = True
+    d = np.zeros(N)
+    np.add.at(d, inst.load_node, np.asarray(inst.load_d)[:, 0])
+    nv = G + (K + 1) * N
+    eq, rhs, ineq, bound = [], [], [], []
+    for k in range(K + 1):
+        F = np.zeros((L, nv))                     # flow into the to node
+        F[np.arange(L), G + k * N + frm] += sus[k]
+        F[np.arange(L), G + k * N + to] -= sus[k]
+        B = np.zeros((N, nv))                     # net injection at each node
+        B[inst.gen_node, np.arange(G)] += 1.0
+        np.add.at(B, to, F)
+        np.subtract.at(B, frm, F)
+        eq.append(B)
+        rhs.append(d)
+        ineq += [F, -F]
+        bound += [cap[k], cap[k]]
+        if k > 0:
+            for n in np.nonzero(dev)[0]:
+                r = np.zeros((1, nv))
+                r[0, G + k * N + n], r[0, G + n] = 1.0, -1.0
+                eq.append(r)
+                rhs.append(np.zeros(1))
+    r = np.zeros((1, nv))
+    r[0, G] = 1.0                                 # reference phase
+    eq.append(r)
+    rhs.append(np.zeros(1))
+    A, b = np.vstack(eq), np.concatenate(rhs)
+    _, R, piv = qr(A.T, pivoting=True, mode="economic")
+    keep = np.sort(piv[:int((np.abs(np.diag(R)) > 1e-9 * abs(R[0, 0])).sum())])
+    A, b = A[keep], b[keep]
+    C, c = np.vstack(ineq), np.concatenate(bound)
+    h = np.zeros(nv)
+    h[:G] = 2 * np.asarray(inst.gen_c2)
+    f = np.zeros(nv)
+    f[:G] = inst.gen_c1
+    pmin, pmax = np.asarray(inst.gen_pmin)[:, 0], np.asarray(inst.gen_pmax)[:, 0]
+    x0 = np.zeros(nv)
+    x0[:G] = pmax * d.sum() / pmax.sum()
+    res = minimize(lambda x: 0.5 * x @ (h * x) + f @ x, x0, jac=lambda x: h * x + f,
+                   method="SLSQP", bounds=[(lo, hi) for lo, hi in zip(pmin, pmax)] + [(None, None)] * (nv - G),
+                   constraints=[dict(type="eq", fun=lambda x: A @ x - b, jac=lambda x: A),
+                                dict(type="ineq", fun=lambda x: c - C @ x, jac=lambda x: -C)],
+                   options=dict(ftol=1e-15, maxiter=3000))
+    assert res.success, res.message
+    return res.x[:G], float(res.fun)
+
+
+def test_contingency_model_matches_phase_coupled_qp():
+    """N-1 contingencies (Section 2.3) on a 14-node grid with 9 device-free
+    nodes: the converged dispatch and cost equal the exact optimum of the
+    contingency-constrained problem, which the contingencies make dearer
+    than the base-case-only optimum."""
+    inst = synth.make_instance("scopf", N=14, L=22, G=4, D=5, B=0, T=1, K=3, seed=3)
+    s = Solver(inst, Options(eps=1e-9, max_iter=100000))
+    r = s.solve()
+    assert r.converged
+    x, obj = _coupled_qp(inst)
+    assert abs(r.objective - obj) <= 1e-6 * abs(obj)
+    np.testing.assert_allclose(s.dispatch()[:inst.G, 0].numpy(), x, atol=1e-5)
+    base = inst.copy()
+    base.K, base.outage = 0, np.zeros(0, np.int32)
+    assert _coupled_qp(base)[1] < obj - 1e-3 * abs(obj)
+
+
+def _small_changes():
+    base = synth.make_instance("chg", N=20, L=30, G=4, D=10, B=2, T=3, K=4, seed=21)
+    return base, synth.with_contingency_changes(base, seed=4, second_outages=1, rating_changes=4,
+                                                sus_changes=3)
+
+
+def test_changed_parameters_hold_at_every_iterate():
+    """General per-contingency parameters (Section 2.3): after every
+    iteration each line of contingency k carries sus_kl (theta1 - theta2)
+    within cap_kl, with sus_kl, cap_kl written out from the change list (a
+    line taken out carries nothing)."""
+    _, inst = _small_changes()
+    sus, cap = _line_params_by_hand(inst)
+    s = Solver(inst, Options(eps=1e-12))
+    for _ in range(15):
+        s.step()
+        st = s.canonical_state()
+        P, d = st["P"].numpy(), (st["TH1"] - st["TH2"]).numpy()
+        np.testing.assert_allclose(P, sus[:, :, None] * d, rtol=0, atol=1e-12)
+        assert np.all(np.abs(P) <= cap[:, :, None] + 1e-15)
+    # the changed susceptances are the ones in force (not the base values)
+    base_sus = np.asarray(inst.line_sus, float)
+    k, l = inst.chg_k, inst.chg_line
+    live = inst.chg_sus > 0
+    gap = np.abs(P[k, l] - base_sus[l][:, None] * d[k, l])
+    assert np.all(gap[live & (inst.chg_sus != base_sus[l])].max(1) > 1e-6)
+    assert np.all(P[k[~live], l[~live]] == 0) and np.any(d[k[~live], l[~live]] != 0)
+
+
+def test_change_to_zero_is_an_outage_and_base_values_change_nothing():
+    """A change to (0, 0) is the N-1 outage written another way; a change to
+    the base values is no change."""
+    base = synth.make_instance("chg0", N=20, L=30, G=4, D=10, B=2, T=3, K=4, seed=21)
+    a = Solver(base, Options(eps=1e-12))
+    a.run(30)
+    b_inst = base.copy()
+    l = int(b_inst.outage[1])
+    b_inst.outage[1] = -1
+    free = [q for q in range(base.L) if q not in set(base.outage.tolist())][:3]
+    b_inst.chg_k = np.array([2, 1, 3, 4], np.int32)
+    b_inst.chg_line = np.array([l] + free, np.int32)
+    b_inst.chg_sus = np.r_[0.0, np.asarray(base.line_sus)[free]]
+    b_inst.chg_cap = np.r_[0.0, np.asarray(base.line_cap)[free]]
+    b = Solver(b_inst, Options(eps=1e-12))
+    b.run(30)
+    sa, sb = a.canonical_state(), b.canonical_state()
+    for f in sa:
+        assert torch.equal(sa[f], sb[f]), f
+
+
+def test_contingency_order_does_not_matter():
+    """Relabelling the contingencies (outages and changes together) relabels
+    the iterate and leaves the contingency means, hence the device
+    schedules, unchanged up to the order of summation."""
+    _, inst = _small_changes()
+    perm = np.array([3, 1, 4, 2])                 # new contingency i+1 is old perm[i]
+    q = inst.copy()
+    q.outage = np.asarray(inst.outage)[perm - 1]
+    inv = np.zeros(inst.K + 1, int)
+    inv[perm] = np.arange(1, inst.K + 1)
+    q.chg_k = inv[inst.chg_k].astype(np.int32)
+    a, b = Solver(inst, Options(eps=1e-12)), Solver(q, Options(eps=1e-12))
+    a.run(25)
+    b.run(25)
+    sa, sb = a.canonical_state(), b.canonical_state()
+    order = np.r_[0, perm]
+    for f in ["P", "TH1", "TH2", "V1", "U", "PBAR", "THBAR"]:
+        torch.testing.assert_close(sb[f], sa[f][order], rtol=1e-11, atol=1e-13)
+    torch.testing.assert_close(sb["PNC"], sa["PNC"], rtol=1e-11, atol=1e-13)
+
+
 def _ptdf(N, frm, to, sus):
     Bm = np.zeros((N, N))
     for f, t, b in zip(frm, to, sus):
