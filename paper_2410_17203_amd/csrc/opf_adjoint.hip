@@ -53,7 +53,7 @@ __device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, int t, i
   const R aw = a.avw[size_t(n) * tp.T + t] * iKp;
   const R at = a.avt[size_t(n) * tp.T + t] * iKp;
   const R su = R(a.s.su_next);
-  const R idg = R(1) / R(tp.deg[n]);
+  const R idg = R(tp.inv_deg[n]);
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
     const bool valid = k0 + e < tp.Kp;
@@ -101,10 +101,10 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
     const VR V2 = *reinterpret_cast<const VR*>(a.A.V2 + ol);
     const VR Wx = *reinterpret_cast<const VR*>(a.A.W + oo);
     const VR Bx = *reinterpret_cast<const VR*>(a.A.TB + oo);
-    const R s = R(tp.sus[l]), cap = R(tp.cap[l]);
+    const R inv2s = R(tp.hinv_sus[l]), cap = R(tp.cap[l]);
     LineOut<R, VEC> o;
     line_prox<R, R, VEC>(P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx, to_end ? Bx : Bo,
-                         to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, s, cap, rp, rt, sv, o);
+                         to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, inv2s, cap, rp, rt, sv, o);
     // (networks of the general line model are rejected by the tape)
     NodeAdj<R, VEC> far;
     node_adj<R, VEC>(a, oo, m, t, k0, far);
@@ -112,9 +112,8 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
     const VR Tmb = *reinterpret_cast<const VR*>(a.out.Tm + ol);
     const VR V1b = *reinterpret_cast<const VR*>(a.out.V1 + ol);
     const VR V2b = *reinterpret_cast<const VR*>(a.out.V2 + ol);
-    const R inv2s = R(0.5) / s;
-    const R den = R(2) * rp + R(2) * rt * inv2s * inv2s;
-    const R ca = rp / den, cb = rt * inv2s / den;
+    const R iden = R(1) / (R(2) * rp + R(2) * rt * inv2s * inv2s);
+    const R ca = rp * iden, cb = rt * inv2s * iden;
     VR Pi, Ti, V1i, V2i;
     double* gc = a.gcap + ol;
 #pragma unroll

@@ -107,6 +107,7 @@ struct TapePlan {
 struct InstPlan {
   size_t ctl, ring;
   size_t line_from, line_to, sus, cap, outage_k, node_lptr, node_lterm, node_nptr, node_nterm, deg,
+      inv_deg, hinv_sus,
       nc_node, ramp_idx, gen_c2, gen_c1, gen_pmin, gen_pmax, gen_ramp, load_d, bat_P, bat_dur,
       bat_eta, bat_alpha;
   size_t part_sweep, part_nc;
@@ -413,6 +414,8 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
   p.node_nptr = L.take((Ni + 1) * 4);
   p.node_nterm = L.take(size_t(s.Jnc) * 4);
   p.deg = L.take(Ni * 8);
+  p.inv_deg = L.take(Ni * 8);
+  p.hinv_sus = L.take(Li * 8);
   p.clus_n0 = L.take((Ni + 1) * 4);
   p.tl_ptr = L.take((Ni + 1) * 4);
   p.tl = L.take(2 * Li * 16);
@@ -902,6 +905,11 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   HIP_TRY(c, up(p.node_nptr, nptr.data(), size_t(N + 1) * 4));
   HIP_TRY(c, up(p.node_nterm, nterm.data(), nterm.size() * 4));
   HIP_TRY(c, up(p.deg, deg.data(), size_t(N) * 8));
+  std::vector<double> inv_deg(N), hinv_sus(L);
+  for (int v = 0; v < N; ++v) inv_deg[v] = 1.0 / deg[v];
+  for (int l = 0; l < L; ++l) hinv_sus[l] = 0.5 / sus[l];
+  HIP_TRY(c, up(p.inv_deg, inv_deg.data(), size_t(N) * 8));
+  HIP_TRY(c, up(p.hinv_sus, hinv_sus.data(), size_t(L) * 8));
   if (tiles_ok) {
     HIP_TRY(c, up(p.clus_n0, clus_n0.data(), clus_n0.size() * 4));
     HIP_TRY(c, up(p.tl_ptr, tl_ptr.data(), tl_ptr.size() * 4));
@@ -936,6 +944,8 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   tp.node_nptr = reinterpret_cast<const int32_t*>(ws + p.node_nptr);
   tp.node_nterm = reinterpret_cast<const int32_t*>(ws + p.node_nterm);
   tp.deg = reinterpret_cast<const double*>(ws + p.deg);
+  tp.inv_deg = reinterpret_cast<const double*>(ws + p.inv_deg);
+  tp.hinv_sus = reinterpret_cast<const double*>(ws + p.hinv_sus);
   tp.clus_n0 = reinterpret_cast<const int32_t*>(ws + p.clus_n0);
   tp.tl_ptr = reinterpret_cast<const int32_t*>(ws + p.tl_ptr);
   tp.tl = reinterpret_cast<const int4*>(ws + p.tl);

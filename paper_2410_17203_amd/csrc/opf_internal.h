@@ -110,6 +110,8 @@ struct Topo {
   const int32_t* node_nptr;   // [N+1] CSR over generator/load/battery ids
   const int32_t* node_nterm;
   const double* deg;          // [N] terminals per node
+  const double* inv_deg;      // [N] 1 / deg
+  const double* hinv_sus;     // [L] 1 / (2 sus) (DC links: 1/2, unused)
   const int32_t* nc_node;     // [Jnc]
   const int32_t* ramp_idx;    // [G] index into ramp inner state, -1 = none
   const double* gen_c2;

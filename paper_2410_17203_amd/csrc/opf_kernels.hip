@@ -170,7 +170,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       } else {
         line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo,
                               to_end ? Wo : Wx[u], to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l,
-                              td_old, k0, tp.Kp, R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+                              td_old, k0, tp.Kp, R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
       }
       if (!to_end) {  // the from node stores the line's new state
         VR Pn, Tn;
@@ -234,20 +234,20 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
     }
     first = false;
   }
-  const double dg = tp.deg[n];
-  const R rdg = R(dg);
+  const double dg = tp.deg[n], idg = tp.inv_deg[n];
+  const R rdg = R(dg), ridg = R(idg);
   VR Un, Wn, Bn;
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
     const bool valid = k0 + e < tp.Kp;
-    const R pb = sp[e] / rdg;
-    const R tb = sb[e] / rdg;
+    const R pb = div_by(sp[e], rdg, ridg);
+    const R tb = div_by(sb[e], rdg, ridg);
     const R un = Uo.x[e] + pb;
     const R wn = un + pb;
     if (check && valid) {
       const double dpb = double(pb);
       acc[0] += dg * dpb * dpb;
-      acc[1] += fmax(double(s2[e]) - double(s1[e]) * double(s1[e]) / dg, 0.0);
+      acc[1] += fmax(double(s2[e]) - double(s1[e]) * double(s1[e]) * idg, 0.0);
       const double dd = dpb - double(Wo.x[e] - Uo.x[e]);
       acc[2] += dg * dd * dd;
       const double dt = double(tb) - double(Bo.x[e]);
@@ -336,6 +336,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
 #endif
   constexpr int SUB = OPF_PASS_BYTES / int(sizeof(R)) < kChunk ? OPF_PASS_BYTES / int(sizeof(R)) : kChunk;
   constexpr int NVMAX = SUB / VEC;  // vectors per pass row
+  static_assert(NVMAX <= 16 && kTileLines * NVMAX < 4096, "x / nvc by multiply and shift");
   using VR = Vec<R, VEC>;
   using VV = Vec<VT, VEC>;
   using VI = Vec<int32_t, VEC>;
@@ -370,19 +371,21 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
       const int c0 = s0 & ~(kChunk - 1);
       const int w = min(kChunk, Kpp - c0);                 // chunk width
       const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors in this pass
+      // x / nvc as a multiply and shift (exact for nvc <= 16, x < 4096)
+      const uint32_t nvc_mag = (65536u + uint32_t(nvc) - 1u) / uint32_t(nvc);
       // element (item i, vector v) of this pass: base + i * w + v * VEC
       const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
       const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
       lds_barrier();  // sTl written; LDS of the previous chunk no longer read
       for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
-        const int i = x / nvc, v = x - i * nvc;
+        const int i = int((uint32_t(x) * nvc_mag) >> 16), v = x - i * nvc;
         const size_t o = nbase + size_t(n0 + i) * w + v * VEC;
         *reinterpret_cast<VR*>(sW + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.W + o);
         *reinterpret_cast<VR*>(sB + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.TB + o);
       }
       lds_barrier();
       for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
-        const int j = x / nvc, v = x - j * nvc;
+        const int j = int((uint32_t(x) * nvc_mag) >> 16), v = x - j * nvc;
         const int4 e = sTl[j];
         const int l = e.x;
         const int k0 = s0 + v * VEC;
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
         } else {
           line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
-                                R(tp.sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+                                R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
         }
         if (e.y >= 0) {  // the cluster holding the from node stores the line
           VR Pn, Tn;
@@ -468,7 +471,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
       }
       lds_barrier();
       for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
-        const int i = x / nvc, v = x - i * nvc, n = n0 + i;
+        const int i = int((uint32_t(x) * nvc_mag) >> 16), v = x - i * nvc, n = n0 + i;
         const int k0 = s0 + v * VEC;
         R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
 #pragma unroll
@@ -513,21 +516,21 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
         const VR Uo = ld_stream(reinterpret_cast<const VR*>(A.U + on));
         const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
         const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
-        const double dg = tp.deg[n];
-        const R rdg = R(dg);
+        const double dg = tp.deg[n], idg = tp.inv_deg[n];
+        const R rdg = R(dg), ridg = R(idg);
         VR Un, Wn, Bn;
         R sumw = R(0), sumb = R(0);
 #pragma unroll
         for (int q = 0; q < VEC; ++q) {
           const bool valid = k0 + q < tp.Kp;
-          const R pb = sp[q] / rdg;
-          const R tb = sb[q] / rdg;
+          const R pb = div_by(sp[q], rdg, ridg);
+          const R tb = div_by(sb[q], rdg, ridg);
           const R un = Uo.x[q] + pb;
           const R wn = un + pb;
           if (check && valid) {
             const double dpb = double(pb);
             acc[0] += dg * dpb * dpb;
-            acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) / dg, 0.0);
+            acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) * idg, 0.0);
             const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
             acc[2] += dg * dd * dd;
             const double dt = double(tb) - double(Bo.x[q]);
