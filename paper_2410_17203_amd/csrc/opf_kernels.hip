@@ -337,6 +337,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
   constexpr int SUB = OPF_PASS_BYTES / int(sizeof(R)) < kChunk ? OPF_PASS_BYTES / int(sizeof(R)) : kChunk;
   constexpr int NVMAX = SUB / VEC;  // vectors per pass row
   static_assert(NVMAX <= 16 && kTileLines * NVMAX < 4096, "x / nvc by multiply and shift");
+  static_assert(kTileNodes * NVMAX <= kTileBlock, "one node vector per thread and pass");
   using VR = Vec<R, VEC>;
   using VV = Vec<VT, VEC>;
   using VI = Vec<int32_t, VEC>;
@@ -367,6 +368,28 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
     double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
     const R* td_old = A.Td + size_t(t) * Kpp;
     R* td_new = B.Td + size_t(t) * Kpp;
+    // Each thread owns at most one node vector per pass (phases 0 and 2).
+    // Its W and thetabar rows are loaded one pass ahead (in flight during
+    // the previous pass's phase 2) and its price row before phase 1.
+    // node_vec: offset of this thread's node vector in the pass at s0, or -1.
+    auto node_vec = [&](int s0) -> int64_t {
+      const int c0 = s0 & ~(kChunk - 1);
+      const int w = min(kChunk, Kpp - c0);
+      const int nvc = min(SUB, c0 + w - s0) / VEC;
+      if (int(threadIdx.x) >= cn * nvc) return -1;
+      const int i = int((uint32_t(threadIdx.x) * ((65536u + uint32_t(nvc) - 1u) / uint32_t(nvc))) >> 16);
+      const int v = threadIdx.x - i * nvc;
+      return int64_t((size_t(t) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + i) * w + v * VEC);
+    };
+    // (held as native 16-byte vectors so that they stay in registers)
+    u32x4 pW = {0u, 0u, 0u, 0u}, pB = {0u, 0u, 0u, 0u};
+    {
+      const int64_t o = node_vec(0);
+      if (o >= 0) {
+        pW = *reinterpret_cast<const u32x4*>(A.W + o);
+        pB = *reinterpret_cast<const u32x4*>(A.TB + o);
+      }
+    }
     for (int s0 = 0; s0 < Kpp; s0 += SUB) {
       const int c0 = s0 & ~(kChunk - 1);
       const int w = min(kChunk, Kpp - c0);                 // chunk width
@@ -376,12 +399,15 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
       // element (item i, vector v) of this pass: base + i * w + v * VEC
       const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
       const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
+      const bool own = int(threadIdx.x) < cn * nvc;
+      const int ii = int((uint32_t(threadIdx.x) * nvc_mag) >> 16), vv = threadIdx.x - ii * nvc;
       lds_barrier();  // sTl written; LDS of the previous chunk no longer read
-      for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
-        const int i = int((uint32_t(x) * nvc_mag) >> 16), v = x - i * nvc;
-        const size_t o = nbase + size_t(n0 + i) * w + v * VEC;
-        *reinterpret_cast<VR*>(sW + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.W + o);
-        *reinterpret_cast<VR*>(sB + i * SUB + v * VEC) = *reinterpret_cast<const VR*>(A.TB + o);
+      u32x4 pU = {0u, 0u, 0u, 0u};
+      if (own) {
+        *reinterpret_cast<u32x4*>(sW + ii * SUB + vv * VEC) = pW;
+        *reinterpret_cast<u32x4*>(sB + ii * SUB + vv * VEC) = pB;
+        pU = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4*>(A.U + nbase + size_t(n0 + ii) * w + vv * VEC));
       }
       lds_barrier();
       for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
@@ -469,9 +495,16 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
         *reinterpret_cast<VR*>(sTm + j * SUB + v * VEC) = To;
         *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
       }
+      if (s0 + SUB < Kpp) {  // the next pass's node rows, in flight during phase 2
+        const int64_t o = node_vec(s0 + SUB);
+        if (o >= 0) {
+          pW = *reinterpret_cast<const u32x4*>(A.W + o);
+          pB = *reinterpret_cast<const u32x4*>(A.TB + o);
+        }
+      }
       lds_barrier();
-      for (int x = threadIdx.x; x < cn * nvc; x += kTileBlock) {
-        const int i = int((uint32_t(x) * nvc_mag) >> 16), v = x - i * nvc, n = n0 + i;
+      if (own) {
+        const int x = threadIdx.x, i = ii, v = vv, n = n0 + i;
         const int k0 = s0 + v * VEC;
         R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
 #pragma unroll
@@ -513,7 +546,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           first = false;
         }
         const size_t on = nbase + size_t(n) * w + v * VEC;
-        const VR Uo = ld_stream(reinterpret_cast<const VR*>(A.U + on));
+        const VR Uo = __builtin_bit_cast(VR, pU);
         const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
         const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
         const double dg = tp.deg[n], idg = tp.inv_deg[n];
