@@ -792,7 +792,8 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   std::vector<double> deg(N);
   for (int v = 0; v < N; ++v) deg[v] = double(lptr[v + 1] - lptr[v] + nptr[v + 1] - nptr[v]);
   // Clusters of consecutive nodes for the tiled sweep: at most kTileNodes
-  // nodes and kTileLines distinct incident lines each, sized so that one
+  // nodes, kTileLines distinct incident lines and kTileDev devices each,
+  // sized so that one
   // iteration has a few thousand (period, cluster) tiles.  Per cluster, the
   // lines touching it (first occurrence in node and CSR order) with the
   // cluster-local index of each end inside it and the far node otherwise;
@@ -805,17 +806,19 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
     int n0 = 0;
     while (tiles_ok && n0 < N) {
       const int cid = int(clus_n0.size()) - 1;
-      int m = n0, cnt = 0;
+      int m = n0, cnt = 0, ndev = 0;
       while (m < N && m - n0 < cmax) {
         int add = 0;
         for (int q = lptr[m]; q < lptr[m + 1]; ++q)
           if (mark[lterm[2 * size_t(q)] >> 1] != cid) ++add;
         if (cnt + add > kTileLines) break;
+        if (ndev + (nptr[m + 1] - nptr[m]) > kTileDev) break;
+        ndev += nptr[m + 1] - nptr[m];
         for (int q = lptr[m]; q < lptr[m + 1]; ++q) mark[lterm[2 * size_t(q)] >> 1] = cid;
         cnt += add;
         ++m;
       }
-      if (m == n0) {  // one node with more lines than a tile holds
+      if (m == n0) {  // one node with more lines or devices than a tile holds
         tiles_ok = false;
         break;
       }

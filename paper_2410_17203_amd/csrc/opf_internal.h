@@ -46,6 +46,7 @@ constexpr int kChunk = OPF_CHUNK; // contingencies per chunk of the line and nod
 #endif
 constexpr int kTileNodes = OPF_TILE_NODES;  // most nodes in one cluster of the tiled sweep
 constexpr int kTileLines = OPF_TILE_LINES;  // most lines touching one cluster
+constexpr int kTileDev = 128;               // most generators, loads, batteries in one cluster
 #ifndef OPF_TILE_BLOCK
 #define OPF_TILE_BLOCK 512
 #endif

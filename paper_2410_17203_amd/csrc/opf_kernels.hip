@@ -326,8 +326,10 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // registers of the thread that owns the node across the chunks.  Tiles of
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
+// (4 waves per SIMD: two workgroups per CU, the most its LDS footprint allows)
 template <typename R, typename VT, bool GEN>
-__global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
+__global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep_tile(KArgs<R, VT> a) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
   // chunk in FP64), so that the LDS footprint is the same in both precisions
@@ -356,6 +358,13 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
   __shared__ __align__(16) R sH[kTileLines * SUB];
   __shared__ R sRw[kTileNodes * NVMAX], sRb[kTileNodes * NVMAX];
   __shared__ int4 sTl[kTileLines];
+  // the cluster's terminal lists for the node sums, staged once per tile:
+  // line terminals (CSR pointers local to the cluster, entries as in tcsr)
+  // and the devices' power and phase in this period (at most kTileDev: the
+  // clusters are built so)
+  __shared__ int sLp[kTileNodes + 1], sNp[kTileNodes + 1], sTc[2 * kTileLines];
+  __shared__ R sDp[kTileDev], sDt[kTileDev];
+  __shared__ double sDg[kTileNodes], sIdg[kTileNodes];
   __shared__ double sh[kTileBlock / kWave];
   const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(T) * tp.Q);
@@ -365,6 +374,23 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
     const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
     const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
     for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
+    const int lp0 = tp.node_lptr[n0], np0 = tp.node_nptr[n0];
+    const int nlt = tp.node_lptr[n0 + cn] - lp0;  // <= 2 kTileLines (each line has two ends)
+    const int ndt = tp.node_nptr[n0 + cn] - np0;  // <= kTileDev
+    for (int i = threadIdx.x; i <= cn; i += kTileBlock) {
+      sLp[i] = tp.node_lptr[n0 + i] - lp0;
+      sNp[i] = tp.node_nptr[n0 + i] - np0;
+      if (i < cn) {
+        sDg[i] = tp.deg[n0 + i];
+        sIdg[i] = tp.inv_deg[n0 + i];
+      }
+    }
+    for (int q = threadIdx.x; q < nlt; q += kTileBlock) sTc[q] = tp.tcsr[lp0 + q];
+    for (int q = threadIdx.x; q < ndt; q += kTileBlock) {
+      const int jd = tp.node_nterm[np0 + q];
+      sDp[q] = a.st.pnc[size_t(jd) * T + t];
+      sDt[q] = a.st.thnc[size_t(jd) * T + t];
+    }
     double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
     const R* td_old = A.Td + size_t(t) * Kpp;
     R* td_new = B.Td + size_t(t) * Kpp;
@@ -510,8 +536,8 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
 #pragma unroll
         for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
         bool first = true;
-        for (int qq = tp.node_lptr[n]; qq < tp.node_lptr[n + 1]; ++qq) {
-          const int ent = tp.tcsr[qq];
+        for (int qq = sLp[i]; qq < sLp[i + 1]; ++qq) {
+          const int ent = sTc[qq];
           const int j = ent >> 1;
           const bool to_end = ent & 1;
           const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + v * VEC);
@@ -530,10 +556,8 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
           }
           first = false;
         }
-        for (int qq = tp.node_nptr[n]; qq < tp.node_nptr[n + 1]; ++qq) {
-          const int jd = tp.node_nterm[qq];
-          const R pj = a.st.pnc[size_t(jd) * T + t];
-          const R thj = a.st.thnc[size_t(jd) * T + t];
+        for (int qq = sNp[i]; qq < sNp[i + 1]; ++qq) {
+          const R pj = sDp[qq], thj = sDt[qq];
 #pragma unroll
           for (int q = 0; q < VEC; ++q) {
             sp[q] += pj;
@@ -549,7 +573,7 @@ __global__ void __launch_bounds__(kTileBlock) k_sweep_tile(KArgs<R, VT> a) {
         const VR Uo = __builtin_bit_cast(VR, pU);
         const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
         const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
-        const double dg = tp.deg[n], idg = tp.inv_deg[n];
+        const double dg = sDg[i], idg = sIdg[i];
         const R rdg = R(dg), ridg = R(idg);
         VR Un, Wn, Bn;
         R sumw = R(0), sumb = R(0);
