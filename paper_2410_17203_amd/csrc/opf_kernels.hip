@@ -392,6 +392,9 @@ k_sweep_tile(KArgs<R, VT> a) {
       sDt[q] = a.st.thnc[size_t(jd) * T + t];
     }
     double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
+    // row sums of the previous pass (prev_nvc vectors per node) wait in sRw,
+    // sRb and are added after the next pass's first barrier
+    int prev_nvc = 0;
     const R* td_old = A.Td + size_t(t) * Kpp;
     R* td_new = B.Td + size_t(t) * Kpp;
     // Each thread owns at most one node vector per pass (phases 0 and 2).
@@ -428,6 +431,12 @@ k_sweep_tile(KArgs<R, VT> a) {
       const bool own = int(threadIdx.x) < cn * nvc;
       const int ii = int((uint32_t(threadIdx.x) * nvc_mag) >> 16), vv = threadIdx.x - ii * nvc;
       lds_barrier();  // sTl written; LDS of the previous chunk no longer read
+      if (threadIdx.x < cn) {
+        for (int v = 0; v < prev_nvc; ++v) {
+          runW += double(sRw[threadIdx.x * prev_nvc + v]);
+          runB += double(sRb[threadIdx.x * prev_nvc + v]);
+        }
+      }
       u32x4 pU = {0u, 0u, 0u, 0u};
       if (own) {
         *reinterpret_cast<u32x4*>(sW + ii * SUB + vv * VEC) = pW;
@@ -605,15 +614,14 @@ k_sweep_tile(KArgs<R, VT> a) {
         sRw[x] = sumw;
         sRb[x] = sumb;
       }
-      lds_barrier();
-      if (threadIdx.x < cn) {
-        for (int v = 0; v < nvc; ++v) {
-          runW += double(sRw[threadIdx.x * nvc + v]);
-          runB += double(sRb[threadIdx.x * nvc + v]);
-        }
-      }
+      prev_nvc = nvc;
     }
+    lds_barrier();
     if (threadIdx.x < cn) {
+      for (int v = 0; v < prev_nvc; ++v) {
+        runW += double(sRw[threadIdx.x * prev_nvc + v]);
+        runB += double(sRb[threadIdx.x * prev_nvc + v]);
+      }
       const size_t o = size_t(n0 + threadIdx.x) * T + t;
       a.st.avgW[o] = R(runW / double(tp.Kp));
       a.st.avgTB[o] = R(runB / double(tp.Kp));
