@@ -99,6 +99,25 @@ def batched_rates(iters, dtype, dual_dtype):
             "algorithmic_elements_per_iteration": elems}
 
 
+def general_model_rate(inst, steps, warmup):
+    """Iterations/s of the FP32 iterate on the same workload extended to the
+    general line model: 3 HVDC links (the paper's network has 3 among about
+    1,150 lines) and per-contingency changes (50 second outages, 100
+    emergency ratings, 50 susceptance changes); the sweep then runs its
+    general-line-model variant."""
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import Solver
+    x = synth.with_contingency_changes(synth.with_dc_links(inst, 3, seed=1), seed=2,
+                                       second_outages=50, rating_changes=100, sus_changes=50)
+    s = Solver(x, dtype="f32", polish_fp64=0, eps=0.0, min_iter=2**31 - 1, max_iter=2**31 - 1)
+    elapsed, kt = time_iterations(s, steps, warmup)
+    sw = kt["sweep"]
+    out = {"dc_links": 3, "changes": int(len(x.chg_k)), "iters_per_s": steps / elapsed,
+           "sweep_ms": sw["ms"] / max(sw["launches"], 1)}
+    s.close()
+    return out
+
+
 def adjoint_times(n_iters, every, dtype):
     """Wall-clock of the recorded forward run and of the adjoint on the
     differentiation workload (gradient of cost + <w, dispatch> w.r.t. load,
@@ -266,6 +285,8 @@ def main():
     ap.add_argument("--batched", type=int, default=1,
                     help="1: also time the 64-instance batch against one-at-a-time solves")
     ap.add_argument("--batched-iters", type=int, default=200)
+    ap.add_argument("--general", type=int, default=1,
+                    help="1: also time the general line model (DC links, per-contingency changes)")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="1: also time 1000 unrolled iterations forward + adjoint (diff workload)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -403,6 +424,11 @@ def main():
             log(f"[bench] batch of {b['instances']} ({b['dual_dtype']} duals): "
                 f"{b['batched_inst_iters_per_s']:.0f} vs {b['one_at_a_time_inst_iters_per_s']:.0f} "
                 f"instance-iterations/s one at a time")
+
+    if args.general:
+        extra["general_line_model"] = general_model_rate(inst, 100, 10)
+        g = extra["general_line_model"]
+        log(f"[bench] general line model: {g['iters_per_s']:.2f} it/s, sweep {g['sweep_ms']:.3f} ms")
 
     if args.adjoint:
         extra["adjoint"] = [adjoint_times(1000, 50, "f32"), adjoint_times(1000, 50, "f64")]
