@@ -158,8 +158,14 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       int dci = -1;
       size_t oh = 0;
       LinePar<R, VEC> lp;
+      // general line model: only DC links and lines with changes need
+      // per-contingency parameters; the others take the N-1 prox
+      bool special = false;
       if constexpr (GEN) {
         dci = tp.line_dc[l];
+        special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
+      }
+      if (special) {
         oh = dci >= 0 ? ck_off(t, dci, k0, tp.Ldc, tp.Kpp) : 0;
         VR Hx{};
         if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
@@ -191,7 +197,7 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
         st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
         st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
         st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-        if constexpr (GEN) {
+        if (special) {
           if (dci >= 0) {
             VR Hn;
 #pragma unroll
@@ -476,8 +482,12 @@ k_sweep_tile(KArgs<R, VT> a) {
         int dci = -1;
         size_t oh = 0;
         LinePar<R, VEC> lp;
+        bool special = false;  // as in the node-row sweep
         if constexpr (GEN) {
           dci = tp.line_dc[l];
+          special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
+        }
+        if (special) {
           oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
                         : 0;
           VR Hx{};
@@ -507,7 +517,7 @@ k_sweep_tile(KArgs<R, VT> a) {
           st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
           st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
           st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-          if constexpr (GEN) {
+          if (special) {
             if (dci >= 0) {
               VR Hn;
 #pragma unroll
