@@ -72,7 +72,8 @@ typedef struct {
   int32_t use_graphs;         /* 1: opf_solve replays captured graph blocks      */
   void* hip_stream;           /* hipStream_t for all work; NULL = null stream    */
   int32_t sweep_tiles;        /* sweep over clusters of consecutive nodes:
-                                 -1 when N*T >= 65536 (default), 0 never, 1 always */
+                                 -1 when N*T*Kpp >= 2^22 (default), 0 never,
+                                 1 always */
 } opf_options;
 
 /* Fills *opt with the defaults above (F64 state, eps = 1e-3 relative,

@@ -332,7 +332,10 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resid
   // by default the tiled sweep runs on instances large enough to fill the
   // chip with (period, cluster) tiles; small ones are launch-bound and keep
   // the node-row sweep
-  const bool want_tiles = c->tile_mode < 0 ? int64_t(s.N) * s.T >= 65536 : c->tile_mode == 1;
+  // (measured crossover: node rows win up to about 3e6 node-contingency-
+  // periods per sweep, tiles from about 6e6)
+  const bool want_tiles =
+      c->tile_mode < 0 ? int64_t(s.N) * s.T * s.Kpp >= (int64_t(1) << 22) : c->tile_mode == 1;
   if (!c->batch && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
     const int64_t items = int64_t(s.T) * s.topo.Q;
     const int cap = std::min(kMaxSweepBlocks,
