@@ -119,3 +119,38 @@ def test_calls_before_load_are_state_errors(lib):
     r = binding.Resid()
     assert lib.opf_residuals(ctx, ctypes.byref(r)) == -4
     lib.opf_destroy(ctx)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (compiled from include/opf.h with the host C compiler)."""
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"opf_options": binding.Options, "opf_network": binding.Network,
+               "opf_resid": binding.Resid, "opf_tuning": binding.Tuning,
+               "opf_layout": binding.Layout}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "opf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
