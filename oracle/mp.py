@@ -42,7 +42,16 @@ Readings of the paper used here (each also listed in the design notes):
     copies beta and scaled duals lambda of penalty omega = scale * rho_hat,
     (beta, lambda) start at zero and are carried across outer iterations,
     lambda is rescaled with omega, and the x-iterate of the last inner
-    iteration is returned.
+    iteration is returned;
+  * an HVDC link (Section 2.1 names it without a cost) is lossless power
+    transfer within its capacity with no phase relation: its prox takes the
+    clipped midpoint (z2 - z1)/2 as the flow and leaves both phases at their
+    targets;
+  * general contingency parameters (Section 2.3): a listed (k, line) pair
+    overrides the base susceptance and capacity in contingency k; a zero
+    susceptance takes an AC line out, and a DC link uses only the capacity;
+  * a curtailable load is a generator with pmin = -d < pmax = 0 and a
+    linear cost (c2 = 0).
 """
 from __future__ import annotations
 
