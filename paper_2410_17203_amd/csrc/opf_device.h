@@ -15,8 +15,8 @@
 #ifndef OPF_NT
 #define OPF_NT 1
 #endif
-// Line terminals of a node taken per step of the sweep (1 or 2): all loads of
-// a step are issued before any of them is used.
+// Line terminals of a node taken per step of the single-instance node-row
+// sweep (1 or 2): all loads of a step are issued before any of them is used.
 #ifndef OPF_SWEEP_BATCH
 #define OPF_SWEEP_BATCH 1
 #endif

@@ -102,8 +102,10 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
 // contingencies.  acc: FP64 residual partials [sum |n| pbar^2, sum theta
 // tilde^2, sum |n| dpbar^2, sum |n| dthetabar^2, sum over lines of 2 dP^2].
 // GEN: the general line model (DC links, per-contingency changes); the plain
-// N-1 model otherwise.
-template <typename R, typename VT, bool GEN>
+// N-1 model otherwise.  NB: line terminals per step, whose loads are all
+// issued before any is used (2 pays in batches, where occupancy is already
+// set by the registers; 1 for single instances).
+template <typename R, typename VT, bool GEN, int NB>
 __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, const Buf<R, VT>& B,
                                  int row, int v, int q0, int q1, bool check, R rp, R rt, R sv,
                                  double (&acc)[5], R& sumw, R& sumb) {
@@ -128,7 +130,6 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
 #pragma unroll
   for (int e = 0; e < VEC; ++e) sp[e] = sb[e] = c[e] = s1[e] = s2[e] = R(0);
   bool first = true;
-  constexpr int NB = OPF_SWEEP_BATCH;
   for (int q = q0; q < q1; q += NB) {
     int2 term[NB];
     VR P[NB], Tm[NB], Wx[NB], Bx[NB];
@@ -300,7 +301,8 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT, GEN>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, GEN, OPF_SWEEP_BATCH>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv,
+                                               acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
@@ -867,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
       const int n = int(row) - (int(row) / a.tp.N) * a.tp.N;
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       for (int v = q; v < nv; v += lpr)
-        sweep_vec<R, VT, GEN>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
+        sweep_vec<R, VT, GEN, 2>(a, A, B, int(row), v, q0, q1, check, rp, rt, sv, acc, sumw, sumb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       sumw += __shfl_xor(sumw, d);
