@@ -213,6 +213,21 @@ def test_dc_link_solve_matches_oracle(dtype):
     s.close()
 
 
+def test_fp32_to_fp64_switch_carries_links_and_changes():
+    """The FP32 -> FP64 switch of the polish widens every part of the iterate,
+    including the half phase differences of DC links and of lines taken out
+    by per-contingency changes: forced at the first check (after 50
+    iterations), the FP64 continuation still matches the oracle after 200."""
+    say("[polish switch] changes_dc")
+    from paper_2410_17203_amd.binding import Solver
+    ref, _ = oracle_run("changes_dc", 200, 10)
+    s = Solver(make("changes_dc"), dtype="f32", eps=1e-12, max_iter=200, polish_factor=1e30)
+    r = s.solve()
+    assert r["iter"] == 200 and r["precision"] == 0
+    compare_fields(s, ref, 1e-4)
+    s.close()
+
+
 def test_fp32_solve_with_fp64_polish_reaches_tolerance():
     say("[solve f32+polish] tiny")
     inst = make("tiny")
