@@ -308,12 +308,17 @@ opf_status opf_state_size(opf_ctx* ctx, size_t* bytes);
  * or device memory, >= opf_state_size bytes).  Synchronises. */
 opf_status opf_get_state(opf_ctx* ctx, void* dst, size_t bytes);
 
-/* Warm start: replaces the iterate with one exported by opf_get_state from a
- * network of the same shape (the data, e.g. loads or capacities, may
- * differ), continues with its penalties, and restarts the iteration count
- * at 0.  The exported precision must be one this context holds.  Rejects
- * foreign or mismatched blobs with OPF_E_INVALID before changing anything.
- * Synchronises. */
+/* Warm start (Section 3.4): replaces the iterate with one exported by
+ * opf_get_state from a network of the same structure (the same sizes, line
+ * ends and kinds, outages, changed pairs and device nodes; the data, e.g.
+ * loads, costs or capacities, may differ), continues with its penalties, and
+ * restarts the iteration count at 0.  The message-passing form needs scaled
+ * prices with u constant over each node's terminals and v summing to zero at
+ * each node: the first holds by construction (one price per node), the
+ * second for any iterate of a run on the same structure, which a
+ * fingerprint in the blob enforces.  The exported precision must be one
+ * this context holds.  Rejects foreign or mismatched blobs with
+ * OPF_E_INVALID before changing anything.  Synchronises. */
 opf_status opf_set_state(opf_ctx* ctx, const void* src, size_t bytes);
 
 /* ---- Derivatives through unrolled iterations (Section 4.4, sensitivities

@@ -62,6 +62,7 @@ struct Inst {
   int N = 0, T = 0, K = 0, Kp = 0, Kpp = 0, L = 0, G = 0, D = 0, B = 0, Jnc = 0, nR = 0;
   int Ldc = 0;  // DC links
   int n_chg = 0, Zc = 0;  // per-contingency changes; those that take a line out
+  uint64_t topo_hash = 0;  // fingerprint of the network's structure
   double eps_eff = 0.0, rms_norm = 1.0;
   Topo topo{};
   Geom geom64{}, geom32{};
@@ -280,6 +281,38 @@ opf_status validate(opf_ctx* c, const opf_network* n) {
   return OPF_OK;
 }
 
+// FNV-1a over the structure of a network (line ends and kinds, outages,
+// changed (contingency, line) pairs, device nodes): an exported iterate can
+// only be imported into a network with the same structure, whose scaled
+// prices then keep their invariants (one price per node, phase duals summing
+// to zero at every node).
+uint64_t topology_hash(const opf_network* n) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t bytes) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  const int32_t sizes[7] = {n->N, n->T, n->K, n->L, n->G, n->D, n->B};
+  mix(sizes, sizeof(sizes));
+  if (n->L > 0) {
+    mix(n->line_from, size_t(n->L) * 4);
+    mix(n->line_to, size_t(n->L) * 4);
+    if (n->line_kind) mix(n->line_kind, size_t(n->L) * 4);
+  }
+  if (n->K > 0) mix(n->outage, size_t(n->K) * 4);
+  if (n->n_chg > 0) {
+    mix(n->chg_k, size_t(n->n_chg) * 4);
+    mix(n->chg_line, size_t(n->n_chg) * 4);
+  }
+  if (n->G > 0) mix(n->gen_node, size_t(n->G) * 4);
+  if (n->D > 0) mix(n->load_node, size_t(n->D) * 4);
+  if (n->B > 0) mix(n->bat_node, size_t(n->B) * 4);
+  return h;
+}
+
 void set_sizes(Inst& s, const opf_network* n) {
   s.N = n->N;
   s.T = n->T;
@@ -295,6 +328,7 @@ void set_sizes(Inst& s, const opf_network* n) {
   if (n->line_kind)
     for (int l = 0; l < n->L; ++l) s.Ldc += n->line_kind[l] == 1;
   s.n_chg = n->n_chg;
+  s.topo_hash = topology_hash(n);
   s.Zc = 0;
   for (int i = 0; i < n->n_chg; ++i) {
     const int l = n->chg_line[i];
@@ -1419,6 +1453,7 @@ struct BlobHead {
   double rho_p, rho_th;
   double su, sv;  // pending rescale ratios (deferred to the next iteration)
   int32_t Ldc, n_chg, Zc;
+  uint64_t topo_hash;
 };
 constexpr size_t kBlobHead = 256;
 static_assert(sizeof(BlobHead) <= kBlobHead, "blob header");
@@ -1917,6 +1952,7 @@ opf_status opf_get_state(opf_ctx* c, void* dst, size_t bytes) {
   hd.Ldc = x.Ldc;
   hd.n_chg = x.n_chg;
   hd.Zc = x.Zc;
+  hd.topo_hash = x.topo_hash;
   hd.rho_p = h.rho_p;
   hd.rho_th = h.rho_th;
   hd.su = h.su;
@@ -1946,6 +1982,10 @@ opf_status opf_set_state(opf_ctx* c, const void* src, size_t bytes) {
       hd.nR != x.nR || hd.B != x.B || hd.Ldc != x.Ldc ||
       hd.n_chg != x.n_chg || hd.Zc != x.Zc)
     return fail(c, OPF_E_INVALID, "state was exported from a network of another shape");
+  if (hd.topo_hash != x.topo_hash)
+    return fail(c, OPF_E_INVALID,
+                "state was exported from a network of another structure (lines, outages or "
+                "device nodes differ)");
   if (!(hd.precision == 0 ? c->has64 : c->has32))
     return fail(c, OPF_E_INVALID, "state precision is not held by this context");
   if (!(hd.rho_p > 0.0 && hd.rho_th > 0.0 && std::isfinite(hd.rho_p) && std::isfinite(hd.rho_th) &&

@@ -121,8 +121,23 @@ def test_import_rejects_mismatched_state():
     bad[:8] = 0
     with pytest.raises(OpfError, match="not a state"):
         a.set_state(bad)
-    a.close()
-    b.close()
+    # same sizes, different wiring: two lines swap their to nodes
+    other = small()
+    lt = np.asarray(other.line_to).copy()
+    i, j = next((i, j) for i in range(len(lt)) for j in range(i + 1, len(lt))
+                if lt[i] != lt[j] and other.line_from[i] != lt[j] and other.line_from[j] != lt[i])
+    lt[i], lt[j] = lt[j], lt[i]
+    other.line_to = lt
+    c = Solver(other, dtype="f64")
+    with pytest.raises(OpfError, match="another structure"):
+        c.set_state(blob)
+    # different loads on the same structure are accepted (a warm start)
+    day2 = small()
+    day2.load_d = np.asarray(day2.load_d) * 1.01
+    d = Solver(day2, dtype="f64")
+    d.set_state(blob)
+    for x in (a, b, c, d):
+        x.close()
 
 
 def test_dc_link_state_view_and_continuation():
