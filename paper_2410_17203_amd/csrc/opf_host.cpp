@@ -139,6 +139,7 @@ struct opf_ctx {
   int64_t* d_dev_prefix = nullptr;
   int64_t* d_grp64 = nullptr;
   int64_t* d_grp32 = nullptr;
+  int64_t* d_tiles = nullptr;
   // launch tuning
   int lanes_shift = 0;       // lanes per row = natural value << shift (or >>)
   double grid_factor = 1.0;  // sweep grid = resident blocks * factor
@@ -490,7 +491,7 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
 }
 
 struct BatchPlan {
-  size_t descs64, descs32, dev_prefix, grp64, grp32;
+  size_t descs64, descs32, dev_prefix, grp64, grp32, tiles;
 };
 
 void plan_batch(int count, Layout& L, BatchPlan& b) {
@@ -499,6 +500,7 @@ void plan_batch(int count, Layout& L, BatchPlan& b) {
   b.dev_prefix = L.take(sizeof(int64_t) * (count + 1));
   b.grp64 = L.take(sizeof(int64_t) * (count + 1));
   b.grp32 = L.take(sizeof(int64_t) * (count + 1));
+  b.tiles = L.take(sizeof(int64_t) * (count + 1));
 }
 
 template <typename R, typename VT>
@@ -660,6 +662,9 @@ opf_status refresh_geometry(opf_ctx* c) {
     res64 = sweep_batch_resident_blocks<double, double>();
     res32 = c->bf16_duals ? sweep_batch_resident_blocks<float, bf16_t>()
                           : sweep_batch_resident_blocks<float, float>();
+    tile64 = tile_batch_resident_blocks<double, double>();
+    tile32 = c->bf16_duals ? tile_batch_resident_blocks<float, bf16_t>()
+                           : tile_batch_resident_blocks<float, float>();
   } else {
     res64 = sweep_resident_blocks<double, double>();
     res32 = c->bf16_duals ? sweep_resident_blocks<float, bf16_t>()
@@ -678,7 +683,12 @@ opf_status refresh_geometry(opf_ctx* c) {
   }
   if (!c->batch) return OPF_OK;
   const int n = int(c->inst.size());
-  std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0);
+  std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0), tiles(n + 1, 0);
+  // the batch takes the tiled sweep over all instances' tiles when every
+  // instance has clusters and (by default) the batch's work per sweep is
+  // that of a large instance
+  bool all_tiles = true;
+  int64_t work = 0;
   std::vector<KArgs<double, double>> d64(n);
   std::vector<KArgs<float, float>> d32(n);
   std::vector<KArgs<float, bf16_t>> d32b(n);
@@ -687,6 +697,9 @@ opf_status refresh_geometry(opf_ctx* c) {
     dev[i + 1] = dev[i] + s.Jnc;
     g64[i + 1] = g64[i] + s.geom64.n_grps;
     g32[i + 1] = g32[i] + s.geom32.n_grps;
+    tiles[i + 1] = tiles[i] + int64_t(s.T) * s.topo.Q;
+    all_tiles = all_tiles && s.topo.Q > 0;
+    work += int64_t(s.N) * s.T * s.Kpp;
     d64[i] = kargs(s, s.st64, s.geom64);
     d32[i] = kargs(s, s.st32, s.geom32);
     d32b[i] = kargs(s, s.st32b, s.geom32);
@@ -705,8 +718,13 @@ opf_status refresh_geometry(opf_ctx* c) {
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_grp32, g32.data(), sizeof(int64_t) * (n + 1),
                             hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  auto tab = [&](BatchTab& t, const void* descs, const int64_t* grp, int64_t total_grps, int res) {
+  const bool want_tiles =
+      all_tiles && (c->tile_mode < 0 ? work >= (int64_t(1) << 22) : c->tile_mode == 1);
+  auto tab = [&](BatchTab& t, const void* descs, const int64_t* grp, int64_t total_grps, int res,
+                 int res_tile) {
     t.descs = descs;
     t.dev_prefix = c->d_dev_prefix;
     t.grp_prefix = grp;
@@ -720,9 +738,16 @@ opf_status refresh_geometry(opf_ctx* c) {
       nb = std::max(8, std::min(nb, std::min(kMaxSweepBlocks,
                                              std::max(8, int(res * c->grid_factor) / 8 * 8))));
     t.n_sweep_blocks = nb;
+    t.tile_prefix = c->d_tiles;
+    t.total_tiles = tiles[n];
+    t.tile_blocks = 0;
+    if (want_tiles && res_tile >= 8)
+      t.tile_blocks = std::max(8, std::min(std::min(kMaxSweepBlocks,
+                                                    std::max(8, int(res_tile * c->grid_factor) / 8 * 8)),
+                                           round8(tiles[n])));
   };
-  tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64);
-  tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32);
+  tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64, tile64);
+  tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32, tile32);
   return OPF_OK;
 }
 
@@ -838,7 +863,10 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   std::vector<int32_t> clus_n0(1, 0), tl_ptr(1, 0), tl, tcsr(2 * size_t(L), 0);
   bool tiles_ok = N > 0;
   {
-    const int cmax = int(std::min<int64_t>(kTileNodes, std::max<int64_t>(8, int64_t(N) * T / 4096)));
+    // (a batch fills the chip with the tiles of all its instances: full tiles)
+    const int cmax = c->batch ? kTileNodes
+                              : int(std::min<int64_t>(kTileNodes,
+                                                      std::max<int64_t>(8, int64_t(N) * T / 4096)));
     std::vector<int32_t> mark(L, -1), pos(L, 0);
     int n0 = 0;
     while (tiles_ok && n0 < N) {
@@ -1084,6 +1112,7 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
     c->d_dev_prefix = reinterpret_cast<int64_t*>(c->ws + bp.dev_prefix);
     c->d_grp64 = reinterpret_cast<int64_t*>(c->ws + bp.grp64);
     c->d_grp32 = reinterpret_cast<int64_t*>(c->ws + bp.grp32);
+    c->d_tiles = reinterpret_cast<int64_t*>(c->ws + bp.tiles);
   }
   s = refresh_geometry(c);
   if (s != OPF_OK) return s;

@@ -203,6 +203,9 @@ struct BatchTab {
   int32_t n_inst;
   int32_t n_sweep_blocks;
   int32_t any_gen;            // some instance has DC links or per-contingency changes
+  int32_t tile_blocks;        // > 0: the tiled sweep over all instances' tiles, with this grid
+  const int64_t* tile_prefix; // [n_inst + 1] prefix of T * Q (tiles) over the instances
+  int64_t total_tiles;
   int64_t total_dev;
   int64_t total_grps;
 };
@@ -212,6 +215,8 @@ template <typename R, typename VT>
 int sweep_resident_blocks();
 template <typename R, typename VT>
 int tile_resident_blocks();
+template <typename R, typename VT>
+int tile_batch_resident_blocks();
 template <typename R, typename VT>
 void launch_devices(const KArgs<R, VT>& a, hipStream_t s);
 template <typename R, typename VT>

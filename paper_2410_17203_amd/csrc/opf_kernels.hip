@@ -334,10 +334,13 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // registers of the thread that owns the node across the chunks.  Tiles of
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
-// (4 waves per SIMD: two workgroups per CU, the most its LDS footprint allows)
+// One tile of the sweep: one period t and cluster cq of the instance a,
+// all contingencies pass by pass; adds the tile's FP64 residual partials to
+// acc.  Called by the single-instance and the batched tiled sweeps.
 template <typename R, typename VT, bool GEN>
-__global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
-k_sweep_tile(KArgs<R, VT> a) {
+__device__ __forceinline__ void tile_item(const KArgs<R, VT>& a, const Buf<R, VT>& A,
+                                          const Buf<R, VT>& B, int t, int cq, R rp, R rt, R sv,
+                                          bool check, double (&acc)[5]) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
   // chunk in FP64), so that the LDS footprint is the same in both precisions
@@ -351,14 +354,7 @@ k_sweep_tile(KArgs<R, VT> a) {
   using VR = Vec<R, VEC>;
   using VV = Vec<VT, VEC>;
   using VI = Vec<int32_t, VEC>;
-  Ctl* ctl = a.g.ctl;
-  if (ctl->done) return;
   const Topo& tp = a.tp;
-  const int cur = ctl->cur;
-  const Buf<R, VT> A = a.st.buf[cur];
-  const Buf<R, VT> B = a.st.buf[cur ^ 1];
-  const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
-  const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
   __shared__ __align__(16) R sW[kTileNodes * SUB];
   __shared__ __align__(16) R sB[kTileNodes * SUB];
   __shared__ __align__(16) R sP[kTileLines * SUB];
@@ -373,271 +369,286 @@ k_sweep_tile(KArgs<R, VT> a) {
   __shared__ int sLp[kTileNodes + 1], sNp[kTileNodes + 1], sTc[2 * kTileLines];
   __shared__ R sDp[kTileDev], sDt[kTileDev];
   __shared__ double sDg[kTileNodes], sIdg[kTileNodes];
-  __shared__ double sh[kTileBlock / kWave];
   const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
-  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(T) * tp.Q);
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t item = sweep.first; item < sweep.end; item += sweep.step) {
-    const int t = int(item / tp.Q), cq = int(item - int64_t(t) * tp.Q);
-    const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
-    const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
-    for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
-    const int lp0 = tp.node_lptr[n0], np0 = tp.node_nptr[n0];
-    const int nlt = tp.node_lptr[n0 + cn] - lp0;  // <= 2 kTileLines (each line has two ends)
-    const int ndt = tp.node_nptr[n0 + cn] - np0;  // <= kTileDev
-    for (int i = threadIdx.x; i <= cn; i += kTileBlock) {
-      sLp[i] = tp.node_lptr[n0 + i] - lp0;
-      sNp[i] = tp.node_nptr[n0 + i] - np0;
-      if (i < cn) {
-        sDg[i] = tp.deg[n0 + i];
-        sIdg[i] = tp.inv_deg[n0 + i];
-      }
+  const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
+  const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
+  for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
+  const int lp0 = tp.node_lptr[n0], np0 = tp.node_nptr[n0];
+  const int nlt = tp.node_lptr[n0 + cn] - lp0;  // <= 2 kTileLines (each line has two ends)
+  const int ndt = tp.node_nptr[n0 + cn] - np0;  // <= kTileDev
+  for (int i = threadIdx.x; i <= cn; i += kTileBlock) {
+    sLp[i] = tp.node_lptr[n0 + i] - lp0;
+    sNp[i] = tp.node_nptr[n0 + i] - np0;
+    if (i < cn) {
+      sDg[i] = tp.deg[n0 + i];
+      sIdg[i] = tp.inv_deg[n0 + i];
     }
-    for (int q = threadIdx.x; q < nlt; q += kTileBlock) sTc[q] = tp.tcsr[lp0 + q];
-    for (int q = threadIdx.x; q < ndt; q += kTileBlock) {
-      const int jd = tp.node_nterm[np0 + q];
-      sDp[q] = a.st.pnc[size_t(jd) * T + t];
-      sDt[q] = a.st.thnc[size_t(jd) * T + t];
+  }
+  for (int q = threadIdx.x; q < nlt; q += kTileBlock) sTc[q] = tp.tcsr[lp0 + q];
+  for (int q = threadIdx.x; q < ndt; q += kTileBlock) {
+    const int jd = tp.node_nterm[np0 + q];
+    sDp[q] = a.st.pnc[size_t(jd) * T + t];
+    sDt[q] = a.st.thnc[size_t(jd) * T + t];
+  }
+  double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
+  // row sums of the previous pass (prev_nvc vectors per node) wait in sRw,
+  // sRb and are added after the next pass's first barrier
+  int prev_nvc = 0;
+  const R* td_old = A.Td + size_t(t) * Kpp;
+  R* td_new = B.Td + size_t(t) * Kpp;
+  // Each thread owns at most one node vector per pass (phases 0 and 2).
+  // Its W and thetabar rows are loaded one pass ahead (in flight during
+  // the previous pass's phase 2) and its price row before phase 1.
+  // node_vec: offset of this thread's node vector in the pass at s0, or -1.
+  auto node_vec = [&](int s0) -> int64_t {
+    const int c0 = s0 & ~(kChunk - 1);
+    const int w = min(kChunk, Kpp - c0);
+    const int nvc = min(SUB, c0 + w - s0) / VEC;
+    if (int(threadIdx.x) >= cn * nvc) return -1;
+    const int i = int((uint32_t(threadIdx.x) * ((65536u + uint32_t(nvc) - 1u) / uint32_t(nvc))) >> 16);
+    const int v = threadIdx.x - i * nvc;
+    return int64_t((size_t(t) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + i) * w + v * VEC);
+  };
+  // (held as native 16-byte vectors so that they stay in registers)
+  u32x4 pW = {0u, 0u, 0u, 0u}, pB = {0u, 0u, 0u, 0u};
+  {
+    const int64_t o = node_vec(0);
+    if (o >= 0) {
+      pW = *reinterpret_cast<const u32x4*>(A.W + o);
+      pB = *reinterpret_cast<const u32x4*>(A.TB + o);
     }
-    double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
-    // row sums of the previous pass (prev_nvc vectors per node) wait in sRw,
-    // sRb and are added after the next pass's first barrier
-    int prev_nvc = 0;
-    const R* td_old = A.Td + size_t(t) * Kpp;
-    R* td_new = B.Td + size_t(t) * Kpp;
-    // Each thread owns at most one node vector per pass (phases 0 and 2).
-    // Its W and thetabar rows are loaded one pass ahead (in flight during
-    // the previous pass's phase 2) and its price row before phase 1.
-    // node_vec: offset of this thread's node vector in the pass at s0, or -1.
-    auto node_vec = [&](int s0) -> int64_t {
-      const int c0 = s0 & ~(kChunk - 1);
-      const int w = min(kChunk, Kpp - c0);
-      const int nvc = min(SUB, c0 + w - s0) / VEC;
-      if (int(threadIdx.x) >= cn * nvc) return -1;
-      const int i = int((uint32_t(threadIdx.x) * ((65536u + uint32_t(nvc) - 1u) / uint32_t(nvc))) >> 16);
-      const int v = threadIdx.x - i * nvc;
-      return int64_t((size_t(t) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + i) * w + v * VEC);
-    };
-    // (held as native 16-byte vectors so that they stay in registers)
-    u32x4 pW = {0u, 0u, 0u, 0u}, pB = {0u, 0u, 0u, 0u};
-    {
-      const int64_t o = node_vec(0);
-      if (o >= 0) {
-        pW = *reinterpret_cast<const u32x4*>(A.W + o);
-        pB = *reinterpret_cast<const u32x4*>(A.TB + o);
-      }
-    }
-    for (int s0 = 0; s0 < Kpp; s0 += SUB) {
-      const int c0 = s0 & ~(kChunk - 1);
-      const int w = min(kChunk, Kpp - c0);                 // chunk width
-      const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors in this pass
-      // x / nvc as a multiply and shift (exact for nvc <= 16, x < 4096)
-      const uint32_t nvc_mag = (65536u + uint32_t(nvc) - 1u) / uint32_t(nvc);
-      // element (item i, vector v) of this pass: base + i * w + v * VEC
-      const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
-      const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
-      const bool own = int(threadIdx.x) < cn * nvc;
-      const int ii = int((uint32_t(threadIdx.x) * nvc_mag) >> 16), vv = threadIdx.x - ii * nvc;
-      lds_barrier();  // sTl written; LDS of the previous chunk no longer read
-      if (threadIdx.x < cn) {
-        for (int v = 0; v < prev_nvc; ++v) {
-          runW += double(sRw[threadIdx.x * prev_nvc + v]);
-          runB += double(sRb[threadIdx.x * prev_nvc + v]);
-        }
-      }
-      u32x4 pU = {0u, 0u, 0u, 0u};
-      if (own) {
-        *reinterpret_cast<u32x4*>(sW + ii * SUB + vv * VEC) = pW;
-        *reinterpret_cast<u32x4*>(sB + ii * SUB + vv * VEC) = pB;
-        pU = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4*>(A.U + nbase + size_t(n0 + ii) * w + vv * VEC));
-      }
-      lds_barrier();
-      for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
-        const int j = int((uint32_t(x) * nvc_mag) >> 16), v = x - j * nvc;
-        const int4 e = sTl[j];
-        const int l = e.x;
-        const int k0 = s0 + v * VEC;
-        const size_t ol = lbase + size_t(l) * w + v * VEC;
-        const VR P = *reinterpret_cast<const VR*>(A.P + ol);
-        const VR Tm = *reinterpret_cast<const VR*>(A.Tm + ol);
-        const VV V1 = *reinterpret_cast<const VV*>(A.V1 + ol);
-        const VV V2 = *reinterpret_cast<const VV*>(A.V2 + ol);
-        const size_t ofar = nbase + size_t(e.w < 0 ? 0 : e.w) * w + v * VEC;
-        VR Wf, Wh, Bf, Bh;
-        if (e.y >= 0) {
-          Wf = *reinterpret_cast<const VR*>(sW + e.y * SUB + v * VEC);
-          Bf = *reinterpret_cast<const VR*>(sB + e.y * SUB + v * VEC);
-        } else {
-          Wf = *reinterpret_cast<const VR*>(A.W + ofar);
-          Bf = *reinterpret_cast<const VR*>(A.TB + ofar);
-        }
-        if (e.z >= 0) {
-          Wh = *reinterpret_cast<const VR*>(sW + e.z * SUB + v * VEC);
-          Bh = *reinterpret_cast<const VR*>(sB + e.z * SUB + v * VEC);
-        } else {
-          Wh = *reinterpret_cast<const VR*>(A.W + ofar);
-          Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
-        }
-        const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
-        LineOut<R, VEC> o;
-        int dci = -1;
-        size_t oh = 0;
-        LinePar<R, VEC> lp;
-        bool special = false;  // as in the node-row sweep
-        if constexpr (GEN) {
-          dci = tp.line_dc[l];
-          special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
-        }
-        if (special) {
-          oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
-                        : 0;
-          VR Hx{};
-          if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
-          line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
-          line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
-        } else {
-          line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
-                                R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
-        }
-        if (e.y >= 0) {  // the cluster holding the from node stores the line
-          VR Pn, Tn;
-          VV V1n, V2n;
-#pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            Pn.x[q] = o.p[q];
-            Tn.x[q] = o.tm[q];
-            V1n.x[q] = DIO<VT, R>::out(o.v1[q]);
-            V2n.x[q] = DIO<VT, R>::out(o.v2[q]);
-            if (ok.x[q] == l) td_new[k0 + q] = o.half[q];
-            if (check) {
-              const double dp = double(o.p[q]) - double(P.x[q]);
-              acc[4] += 2.0 * dp * dp;
-            }
-          }
-          st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
-          st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
-          st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
-          st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-          if (special) {
-            if (dci >= 0) {
-              VR Hn;
-#pragma unroll
-              for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
-              *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
-            }
-#pragma unroll
-            for (int q = 0; q < VEC; ++q)
-              if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
-          }
-        }
-        VR Po, To, Ho;
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          Po.x[q] = o.p[q];
-          To.x[q] = o.tm[q];
-          Ho.x[q] = o.half[q];
-        }
-        *reinterpret_cast<VR*>(sP + j * SUB + v * VEC) = Po;
-        *reinterpret_cast<VR*>(sTm + j * SUB + v * VEC) = To;
-        *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
-      }
-      if (s0 + SUB < Kpp) {  // the next pass's node rows, in flight during phase 2
-        const int64_t o = node_vec(s0 + SUB);
-        if (o >= 0) {
-          pW = *reinterpret_cast<const u32x4*>(A.W + o);
-          pB = *reinterpret_cast<const u32x4*>(A.TB + o);
-        }
-      }
-      lds_barrier();
-      if (own) {
-        const int x = threadIdx.x, i = ii, v = vv, n = n0 + i;
-        const int k0 = s0 + v * VEC;
-        R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
-        bool first = true;
-        for (int qq = sLp[i]; qq < sLp[i + 1]; ++qq) {
-          const int ent = sTc[qq];
-          const int j = ent >> 1;
-          const bool to_end = ent & 1;
-          const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + v * VEC);
-          const VR To = *reinterpret_cast<const VR*>(sTm + j * SUB + v * VEC);
-          const VR Ho = *reinterpret_cast<const VR*>(sH + j * SUB + v * VEC);
-#pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            const R pj = to_end ? Po.x[q] : -Po.x[q];
-            const R thj = to_end ? To.x[q] - Ho.x[q] : To.x[q] + Ho.x[q];
-            sp[q] += pj;
-            sb[q] += thj;
-            if (first) c[q] = thj;
-            const R d = thj - c[q];
-            s1[q] += d;
-            s2[q] += d * d;
-          }
-          first = false;
-        }
-        for (int qq = sNp[i]; qq < sNp[i + 1]; ++qq) {
-          const R pj = sDp[qq], thj = sDt[qq];
-#pragma unroll
-          for (int q = 0; q < VEC; ++q) {
-            sp[q] += pj;
-            sb[q] += thj;
-            if (first) c[q] = thj;
-            const R d = thj - c[q];
-            s1[q] += d;
-            s2[q] += d * d;
-          }
-          first = false;
-        }
-        const size_t on = nbase + size_t(n) * w + v * VEC;
-        const VR Uo = __builtin_bit_cast(VR, pU);
-        const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
-        const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
-        const double dg = sDg[i], idg = sIdg[i];
-        const R rdg = R(dg), ridg = R(idg);
-        VR Un, Wn, Bn;
-        R sumw = R(0), sumb = R(0);
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          const bool valid = k0 + q < tp.Kp;
-          const R pb = div_by(sp[q], rdg, ridg);
-          const R tb = div_by(sb[q], rdg, ridg);
-          const R un = Uo.x[q] + pb;
-          const R wn = un + pb;
-          if (check && valid) {
-            const double dpb = double(pb);
-            acc[0] += dg * dpb * dpb;
-            acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) * idg, 0.0);
-            const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
-            acc[2] += dg * dd * dd;
-            const double dt = double(tb) - double(Bo.x[q]);
-            acc[3] += dg * dt * dt;
-          }
-          Un.x[q] = valid ? un : R(0);
-          Wn.x[q] = valid ? wn : R(0);
-          Bn.x[q] = valid ? tb : R(0);
-          sumw += Wn.x[q];
-          sumb += Bn.x[q];
-        }
-        st_stream(reinterpret_cast<VR*>(B.U + on), Un);
-        st_stream(reinterpret_cast<VR*>(B.W + on), Wn);
-        st_stream(reinterpret_cast<VR*>(B.TB + on), Bn);
-        sRw[x] = sumw;
-        sRb[x] = sumb;
-      }
-      prev_nvc = nvc;
-    }
-    lds_barrier();
+  }
+  for (int s0 = 0; s0 < Kpp; s0 += SUB) {
+    const int c0 = s0 & ~(kChunk - 1);
+    const int w = min(kChunk, Kpp - c0);                 // chunk width
+    const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors in this pass
+    // x / nvc as a multiply and shift (exact for nvc <= 16, x < 4096)
+    const uint32_t nvc_mag = (65536u + uint32_t(nvc) - 1u) / uint32_t(nvc);
+    // element (item i, vector v) of this pass: base + i * w + v * VEC
+    const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
+    const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
+    const bool own = int(threadIdx.x) < cn * nvc;
+    const int ii = int((uint32_t(threadIdx.x) * nvc_mag) >> 16), vv = threadIdx.x - ii * nvc;
+    lds_barrier();  // sTl written; LDS of the previous chunk no longer read
     if (threadIdx.x < cn) {
       for (int v = 0; v < prev_nvc; ++v) {
         runW += double(sRw[threadIdx.x * prev_nvc + v]);
         runB += double(sRb[threadIdx.x * prev_nvc + v]);
       }
-      const size_t o = size_t(n0 + threadIdx.x) * T + t;
-      a.st.avgW[o] = R(runW / double(tp.Kp));
-      a.st.avgTB[o] = R(runB / double(tp.Kp));
     }
+    u32x4 pU = {0u, 0u, 0u, 0u};
+    if (own) {
+      *reinterpret_cast<u32x4*>(sW + ii * SUB + vv * VEC) = pW;
+      *reinterpret_cast<u32x4*>(sB + ii * SUB + vv * VEC) = pB;
+      pU = __builtin_nontemporal_load(
+          reinterpret_cast<const u32x4*>(A.U + nbase + size_t(n0 + ii) * w + vv * VEC));
+    }
+    lds_barrier();
+    for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
+      const int j = int((uint32_t(x) * nvc_mag) >> 16), v = x - j * nvc;
+      const int4 e = sTl[j];
+      const int l = e.x;
+      const int k0 = s0 + v * VEC;
+      const size_t ol = lbase + size_t(l) * w + v * VEC;
+      const VR P = *reinterpret_cast<const VR*>(A.P + ol);
+      const VR Tm = *reinterpret_cast<const VR*>(A.Tm + ol);
+      const VV V1 = *reinterpret_cast<const VV*>(A.V1 + ol);
+      const VV V2 = *reinterpret_cast<const VV*>(A.V2 + ol);
+      const size_t ofar = nbase + size_t(e.w < 0 ? 0 : e.w) * w + v * VEC;
+      VR Wf, Wh, Bf, Bh;
+      if (e.y >= 0) {
+        Wf = *reinterpret_cast<const VR*>(sW + e.y * SUB + v * VEC);
+        Bf = *reinterpret_cast<const VR*>(sB + e.y * SUB + v * VEC);
+      } else {
+        Wf = *reinterpret_cast<const VR*>(A.W + ofar);
+        Bf = *reinterpret_cast<const VR*>(A.TB + ofar);
+      }
+      if (e.z >= 0) {
+        Wh = *reinterpret_cast<const VR*>(sW + e.z * SUB + v * VEC);
+        Bh = *reinterpret_cast<const VR*>(sB + e.z * SUB + v * VEC);
+      } else {
+        Wh = *reinterpret_cast<const VR*>(A.W + ofar);
+        Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
+      }
+      const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+      LineOut<R, VEC> o;
+      int dci = -1;
+      size_t oh = 0;
+      LinePar<R, VEC> lp;
+      bool special = false;  // as in the node-row sweep
+      if constexpr (GEN) {
+        dci = tp.line_dc[l];
+        special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
+      }
+      if (special) {
+        oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
+                      : 0;
+        VR Hx{};
+        if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
+        line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
+        line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
+      } else {
+        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
+                              R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+      }
+      if (e.y >= 0) {  // the cluster holding the from node stores the line
+        VR Pn, Tn;
+        VV V1n, V2n;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          Pn.x[q] = o.p[q];
+          Tn.x[q] = o.tm[q];
+          V1n.x[q] = DIO<VT, R>::out(o.v1[q]);
+          V2n.x[q] = DIO<VT, R>::out(o.v2[q]);
+          if (ok.x[q] == l) td_new[k0 + q] = o.half[q];
+          if (check) {
+            const double dp = double(o.p[q]) - double(P.x[q]);
+            acc[4] += 2.0 * dp * dp;
+          }
+        }
+        st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
+        st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
+        st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
+        st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+        if (special) {
+          if (dci >= 0) {
+            VR Hn;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
+            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+          }
+#pragma unroll
+          for (int q = 0; q < VEC; ++q)
+            if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
+        }
+      }
+      VR Po, To, Ho;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        Po.x[q] = o.p[q];
+        To.x[q] = o.tm[q];
+        Ho.x[q] = o.half[q];
+      }
+      *reinterpret_cast<VR*>(sP + j * SUB + v * VEC) = Po;
+      *reinterpret_cast<VR*>(sTm + j * SUB + v * VEC) = To;
+      *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
+    }
+    if (s0 + SUB < Kpp) {  // the next pass's node rows, in flight during phase 2
+      const int64_t o = node_vec(s0 + SUB);
+      if (o >= 0) {
+        pW = *reinterpret_cast<const u32x4*>(A.W + o);
+        pB = *reinterpret_cast<const u32x4*>(A.TB + o);
+      }
+    }
+    lds_barrier();
+    if (own) {
+      const int x = threadIdx.x, i = ii, v = vv, n = n0 + i;
+      const int k0 = s0 + v * VEC;
+      R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
+      bool first = true;
+      for (int qq = sLp[i]; qq < sLp[i + 1]; ++qq) {
+        const int ent = sTc[qq];
+        const int j = ent >> 1;
+        const bool to_end = ent & 1;
+        const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + v * VEC);
+        const VR To = *reinterpret_cast<const VR*>(sTm + j * SUB + v * VEC);
+        const VR Ho = *reinterpret_cast<const VR*>(sH + j * SUB + v * VEC);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const R pj = to_end ? Po.x[q] : -Po.x[q];
+          const R thj = to_end ? To.x[q] - Ho.x[q] : To.x[q] + Ho.x[q];
+          sp[q] += pj;
+          sb[q] += thj;
+          if (first) c[q] = thj;
+          const R d = thj - c[q];
+          s1[q] += d;
+          s2[q] += d * d;
+        }
+        first = false;
+      }
+      for (int qq = sNp[i]; qq < sNp[i + 1]; ++qq) {
+        const R pj = sDp[qq], thj = sDt[qq];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          sp[q] += pj;
+          sb[q] += thj;
+          if (first) c[q] = thj;
+          const R d = thj - c[q];
+          s1[q] += d;
+          s2[q] += d * d;
+        }
+        first = false;
+      }
+      const size_t on = nbase + size_t(n) * w + v * VEC;
+      const VR Uo = __builtin_bit_cast(VR, pU);
+      const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
+      const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
+      const double dg = sDg[i], idg = sIdg[i];
+      const R rdg = R(dg), ridg = R(idg);
+      VR Un, Wn, Bn;
+      R sumw = R(0), sumb = R(0);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const bool valid = k0 + q < tp.Kp;
+        const R pb = div_by(sp[q], rdg, ridg);
+        const R tb = div_by(sb[q], rdg, ridg);
+        const R un = Uo.x[q] + pb;
+        const R wn = un + pb;
+        if (check && valid) {
+          const double dpb = double(pb);
+          acc[0] += dg * dpb * dpb;
+          acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) * idg, 0.0);
+          const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
+          acc[2] += dg * dd * dd;
+          const double dt = double(tb) - double(Bo.x[q]);
+          acc[3] += dg * dt * dt;
+        }
+        Un.x[q] = valid ? un : R(0);
+        Wn.x[q] = valid ? wn : R(0);
+        Bn.x[q] = valid ? tb : R(0);
+        sumw += Wn.x[q];
+        sumb += Bn.x[q];
+      }
+      st_stream(reinterpret_cast<VR*>(B.U + on), Un);
+      st_stream(reinterpret_cast<VR*>(B.W + on), Wn);
+      st_stream(reinterpret_cast<VR*>(B.TB + on), Bn);
+      sRw[x] = sumw;
+      sRb[x] = sumb;
+    }
+    prev_nvc = nvc;
+  }
+  lds_barrier();
+  if (threadIdx.x < cn) {
+    for (int v = 0; v < prev_nvc; ++v) {
+      runW += double(sRw[threadIdx.x * prev_nvc + v]);
+      runB += double(sRb[threadIdx.x * prev_nvc + v]);
+    }
+    const size_t o = size_t(n0 + threadIdx.x) * T + t;
+    a.st.avgW[o] = R(runW / double(tp.Kp));
+    a.st.avgTB[o] = R(runB / double(tp.Kp));
+  }
+}
+
+// (4 waves per SIMD: two workgroups per CU, the most its LDS footprint allows)
+template <typename R, typename VT, bool GEN>
+__global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep_tile(KArgs<R, VT> a) {
+  Ctl* ctl = a.g.ctl;
+  if (ctl->done) return;
+  const Topo& tp = a.tp;
+  const int cur = ctl->cur;
+  const Buf<R, VT> A = a.st.buf[cur];
+  const Buf<R, VT> B = a.st.buf[cur ^ 1];
+  const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
+  const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
+  __shared__ double sh[kTileBlock / kWave];
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(tp.T) * tp.Q);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t item = sweep.first; item < sweep.end; item += sweep.step) {
+    const int t = int(item / tp.Q), cq = int(item - int64_t(t) * tp.Q);
+    tile_item<R, VT, GEN>(a, A, B, t, cq, rp, rt, sv, check, acc);
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -890,12 +901,57 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
   }
 }
 
+// Tiled sweep over the tiles of all instances of a batch (one work list, in
+// instance order).  A workgroup's tiles of one instance are consecutive in
+// its own sequence, so it writes that instance's residual partials once, in
+// its own slot; it zeroes its slot of every instance it did not visit.
+template <typename R, typename VT, bool GEN>
+__global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep_tile_batch(BatchTab tab) {
+  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  __shared__ double sh[kTileBlock / kWave];
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_tiles);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int first = -1, cur_i = -1;
+  auto flush = [&](int i) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double v = block_sum<kTileBlock>(acc[k], sh);
+      if (threadIdx.x == 0) descs[i].g.part_sweep[5 * blockIdx.x + k] = v;
+      acc[k] = 0.0;
+    }
+  };
+  for (int64_t g = sweep.first; g < sweep.end; g += sweep.step) {
+    const int i = find_inst(tab.tile_prefix, tab.n_inst, g);
+    if (i != cur_i) {
+      if (cur_i >= 0) flush(cur_i);
+      if (first < 0) first = i;
+      cur_i = i;
+    }
+    const KArgs<R, VT>& a = descs[i];
+    Ctl* ctl = a.g.ctl;
+    if (ctl->done) continue;
+    const int cur = ctl->cur;
+    const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
+    const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
+    const int64_t li = g - tab.tile_prefix[i];
+    const int t = int(li / a.tp.Q), cq = int(li - int64_t(t) * a.tp.Q);
+    tile_item<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], t, cq, rp, rt, sv, check, acc);
+  }
+  if (cur_i >= 0) flush(cur_i);
+  for (int q = threadIdx.x; q < 5 * tab.n_inst; q += kTileBlock) {
+    const int i = q / 5;
+    if (first < 0 || i < first || i > cur_i) descs[i].g.part_sweep[5 * blockIdx.x + (q - 5 * i)] = 0.0;
+  }
+}
+
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
   const KArgs<R, VT>& a = descs[blockIdx.x];
   const int64_t ng = tab.grp_prefix[blockIdx.x + 1] - tab.grp_prefix[blockIdx.x];
-  finalize_body(a, int(ng * (kBlock / kWave)), a.tp.Jnc);
+  const int n_sweep = tab.tile_blocks > 0 ? tab.tile_blocks : int(ng * (kBlock / kWave));
+  finalize_body(a, n_sweep, a.tp.Jnc);
 }
 
 template <typename R, typename VT>
@@ -1051,6 +1107,17 @@ int tile_resident_blocks() {
 }
 
 template <typename R, typename VT>
+int tile_batch_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_tile_batch<R, VT, false>,
+                                                   kTileBlock, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+template <typename R, typename VT>
 void launch_finalize(const KArgs<R, VT>& a, hipStream_t s) {
   k_finalize<R, VT><<<1, kBlock, 0, s>>>(a);
 }
@@ -1125,10 +1192,16 @@ void launch_batch_iter_devices(const BatchTab& tab, int max_T, hipStream_t s) {
 
 template <typename R, typename VT>
 void launch_batch_iter_sweep(const BatchTab& tab, hipStream_t s) {
-  if (tab.any_gen)
+  if (tab.tile_blocks > 0) {
+    if (tab.any_gen)
+      k_sweep_tile_batch<R, VT, true><<<tab.tile_blocks, kTileBlock, 0, s>>>(tab);
+    else
+      k_sweep_tile_batch<R, VT, false><<<tab.tile_blocks, kTileBlock, 0, s>>>(tab);
+  } else if (tab.any_gen) {
     k_sweep_batch<R, VT, true><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
-  else
+  } else {
     k_sweep_batch<R, VT, false><<<tab.n_sweep_blocks, kBlock, 0, s>>>(tab);
+  }
 }
 
 template <typename R, typename VT>
@@ -1159,6 +1232,7 @@ int sweep_batch_resident_blocks() {
   template int sweep_batch_resident_blocks<R, VT>();                                 \
   template int sweep_resident_blocks<R, VT>();                                       \
   template int tile_resident_blocks<R, VT>();                                        \
+  template int tile_batch_resident_blocks<R, VT>();                                  \
   template void launch_devices<R, VT>(const KArgs<R, VT>&, hipStream_t);            \
   template void launch_sweep<R, VT>(const KArgs<R, VT>&, hipStream_t);              \
   template void launch_finalize<R, VT>(const KArgs<R, VT>&, hipStream_t);           \

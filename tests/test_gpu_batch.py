@@ -55,11 +55,14 @@ def rel_err(a, b):
     return na if nb == 0.0 else na / nb
 
 
-def test_batched_iterates_match_oracle_per_instance():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_batched_iterates_match_oracle_per_instance(tiles):
+    """Batched node-row sweep (tiles = 0) and batched tiled sweep over all
+    instances' tiles (tiles = 1)."""
     from paper_2410_17203_amd.binding import Solver
-    say("[batch] fp64 vs oracle")
+    say(f"[batch] fp64 vs oracle, tiles={tiles}")
     insts = batch_instances()
-    s = Solver(insts, dtype="f64", adapt_every=0, eps=1e-12)
+    s = Solver(insts, dtype="f64", adapt_every=0, eps=1e-12, sweep_tiles=tiles)
     assert s.num_instances == len(insts)
     s.iterate(150)
     for i in range(len(insts)):
@@ -71,14 +74,15 @@ def test_batched_iterates_match_oracle_per_instance():
     s.close()
 
 
-def test_batched_equals_one_at_a_time():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_batched_equals_one_at_a_time(tiles):
     from paper_2410_17203_amd.binding import Solver
-    say("[batch] batched vs single, adaptive penalty")
+    say(f"[batch] batched vs single, adaptive penalty, tiles={tiles}")
     insts = batch_instances()
-    b = Solver(insts, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0)
+    b = Solver(insts, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0, sweep_tiles=tiles)
     b.iterate(120)
     for i, inst in enumerate(insts):
-        a = Solver(inst, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0)
+        a = Solver(inst, dtype="f64", eps=1e-12, rho_p=0.2, rho_theta=5.0, sweep_tiles=tiles)
         a.iterate(120)
         ha, hb = a.history(), b.history(instance=i)
         assert [(h["rho_p"], h["rho_theta"]) for h in ha] == \
@@ -89,12 +93,13 @@ def test_batched_equals_one_at_a_time():
     b.close()
 
 
-def test_batched_solve_stops_each_instance_on_its_own():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_batched_solve_stops_each_instance_on_its_own(tiles):
     from paper_2410_17203_amd.binding import Solver
-    say("[batch] solve fp32")
+    say(f"[batch] solve fp32, tiles={tiles}")
     insts = batch_instances()
     cap = 6000
-    b = Solver(insts, dtype="f32", eps=1e-3, max_iter=cap)
+    b = Solver(insts, dtype="f32", eps=1e-3, max_iter=cap, sweep_tiles=tiles)
     r = b.solve()
     res = [b.residuals(i) for i in range(len(insts))]
     conv = [x["converged"] for x in res]
@@ -114,7 +119,7 @@ def test_batched_solve_stops_each_instance_on_its_own():
         assert b.residuals(i)["iter"] == x["iter"]
     # each instance stops where its own single-instance solve stops
     for i, inst in enumerate(insts):
-        a = Solver(inst, dtype="f32", eps=1e-3, max_iter=cap, polish_fp64=0)
+        a = Solver(inst, dtype="f32", eps=1e-3, max_iter=cap, polish_fp64=0, sweep_tiles=tiles)
         ra = a.solve()
         assert ra["iter"] == res[i]["iter"] and ra["converged"] == res[i]["converged"]
         assert abs(ra["objective"] - res[i]["objective"]) <= 1e-5 * abs(ra["objective"])
