@@ -71,9 +71,10 @@ typedef struct {
   double polish_factor;       /* [1.2] switch point, as a multiple of eps        */
   int32_t use_graphs;         /* 1: opf_solve replays captured graph blocks      */
   void* hip_stream;           /* hipStream_t for all work; NULL = null stream    */
-  int32_t sweep_tiles;        /* sweep over clusters of consecutive nodes:
-                                 -1 when N*T*Kpp >= 2^22 (default), 0 never,
-                                 1 always */
+  int32_t sweep_tiles;        /* sweep over clusters of consecutive nodes
+                                 (-1 default, or 1) whenever every node has
+                                 at most 128 lines and 128 devices, else node
+                                 rows; 0: node rows always */
 } opf_options;
 
 /* Fills *opt with the defaults above (F64 state, eps = 1e-3 relative,

@@ -364,13 +364,9 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resid
     g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
   }
   g.tile_blocks = 0;
-  // by default the tiled sweep runs on instances large enough to fill the
-  // chip with (period, cluster) tiles; small ones are launch-bound and keep
-  // the node-row sweep
-  // (measured crossover: node rows win up to about 3e6 node-contingency-
-  // periods per sweep, tiles from about 6e6)
-  const bool want_tiles =
-      c->tile_mode < 0 ? int64_t(s.N) * s.T * s.Kpp >= (int64_t(1) << 22) : c->tile_mode == 1;
+  // the tiled sweep whenever the clusters exist (measured faster than the
+  // node rows at every size from 30 nodes up); tile_mode 0 forces node rows
+  const bool want_tiles = c->tile_mode != 0;
   if (!c->batch && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
     const int64_t items = int64_t(s.T) * s.topo.Q;
     const int cap = std::min(kMaxSweepBlocks,
@@ -685,10 +681,8 @@ opf_status refresh_geometry(opf_ctx* c) {
   const int n = int(c->inst.size());
   std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0), tiles(n + 1, 0);
   // the batch takes the tiled sweep over all instances' tiles when every
-  // instance has clusters and (by default) the batch's work per sweep is
-  // that of a large instance
+  // instance has clusters (unless tile_mode forces node rows)
   bool all_tiles = true;
-  int64_t work = 0;
   std::vector<KArgs<double, double>> d64(n);
   std::vector<KArgs<float, float>> d32(n);
   std::vector<KArgs<float, bf16_t>> d32b(n);
@@ -699,7 +693,6 @@ opf_status refresh_geometry(opf_ctx* c) {
     g32[i + 1] = g32[i] + s.geom32.n_grps;
     tiles[i + 1] = tiles[i] + int64_t(s.T) * s.topo.Q;
     all_tiles = all_tiles && s.topo.Q > 0;
-    work += int64_t(s.N) * s.T * s.Kpp;
     d64[i] = kargs(s, s.st64, s.geom64);
     d32[i] = kargs(s, s.st32, s.geom32);
     d32b[i] = kargs(s, s.st32b, s.geom32);
@@ -721,8 +714,7 @@ opf_status refresh_geometry(opf_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int64_t) * (n + 1),
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const bool want_tiles =
-      all_tiles && (c->tile_mode < 0 ? work >= (int64_t(1) << 22) : c->tile_mode == 1);
+  const bool want_tiles = all_tiles && c->tile_mode != 0;
   auto tab = [&](BatchTab& t, const void* descs, const int64_t* grp, int64_t total_grps, int res,
                  int res_tile) {
     t.descs = descs;
@@ -854,19 +846,16 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   std::vector<double> deg(N);
   for (int v = 0; v < N; ++v) deg[v] = double(lptr[v + 1] - lptr[v] + nptr[v + 1] - nptr[v]);
   // Clusters of consecutive nodes for the tiled sweep: at most kTileNodes
-  // nodes, kTileLines distinct incident lines and kTileDev devices each,
-  // sized so that one
-  // iteration has a few thousand (period, cluster) tiles.  Per cluster, the
+  // nodes, kTileLines distinct incident lines and kTileDev devices each
+  // (full-size clusters: smaller ones measured slower at every instance
+  // size, their fixed per-tile costs dominating).  Per cluster, the
   // lines touching it (first occurrence in node and CSR order) with the
   // cluster-local index of each end inside it and the far node otherwise;
   // per line terminal, its line's index in that table.
   std::vector<int32_t> clus_n0(1, 0), tl_ptr(1, 0), tl, tcsr(2 * size_t(L), 0);
   bool tiles_ok = N > 0;
   {
-    // (a batch fills the chip with the tiles of all its instances: full tiles)
-    const int cmax = c->batch ? kTileNodes
-                              : int(std::min<int64_t>(kTileNodes,
-                                                      std::max<int64_t>(8, int64_t(N) * T / 4096)));
+    const int cmax = kTileNodes;
     std::vector<int32_t> mark(L, -1), pos(L, 0);
     int n0 = 0;
     while (tiles_ok && n0 < N) {
