@@ -5,15 +5,19 @@
 //              contingency-averaged targets, one device per wavefront (the
 //              time-coupled ones by an inner ADMM whose tridiagonal solves
 //              are wavefront scans over the horizon).
-//   k_sweep    steps 1 and 3 fused, one (period, node) row of contingencies
-//              per lane group: every line at the node is proxed from the
-//              previous iterate (both end nodes compute it identically, the
-//              from node stores it), then the node averages pbar, thetabar
-//              are formed as CSR-by-node segmented sums in a fixed order (no
-//              atomics), the price u += pbar is updated, and the contingency
-//              averages for step 2 and the FP64 residual partials of Section
-//              3.3 are produced.  The iterate is double-buffered; the device
-//              control block says which buffer is current.
+//   k_sweep_tile  steps 1 and 3 fused over (period, cluster of consecutive
+//              nodes) tiles staged in LDS: every line touching the cluster
+//              is proxed from the previous iterate, then the node averages
+//              pbar, thetabar are formed as CSR-by-node sums in a fixed order
+//              (no atomics), the price u += pbar is updated, and the
+//              contingency averages for step 2 and the FP64 residual partials
+//              of Section 3.3 are produced.  The default.
+//   k_sweep    the same per (period, node) row of contingencies and lane
+//              group, for grids whose clusters cannot be built (both end
+//              nodes prox a line identically, the from node stores it).
+//   *_batch    the same over the instances of a batch, one launch per phase.
+//   The iterate is double-buffered; the device control block says which
+//   buffer is current.
 //   k_finalize FP64 residual norms, the stopping test of eq. converge and the
 //              adaptive penalty of Section 3.5, all on the device.
 //   k_rescale  u <- (rho_old / rho_new) u after a penalty change.
