@@ -345,7 +345,10 @@ def make_instance(name: str, N: int, L: int, G: int, D: int, B: int, T: int, K: 
         load_node=load_node, load_d=demand,
         bat_node=bat_node, bat_P=bat_P, bat_dur=bat_dur, bat_eta=bat_eta,
         bat_alpha=bat_alpha,
-        meta={"seed": seed, "frac_lines_raised": frac, "capacity_scale": scale},
+        meta={"seed": seed, "frac_lines_raised": frac, "capacity_scale": scale,
+              # the reference dispatch [G, T] (batteries idle) that certifies
+              # feasibility with free post-outage phases
+              "ref_dispatch": disp},
     )
 
 

@@ -481,3 +481,66 @@ def test_curtailable_load_sets_the_price():
     p = s.dispatch()[:, 0].numpy()
     np.testing.assert_allclose(p, [1.0, 0.5, -1.5], atol=1e-6)
     np.testing.assert_allclose(s.lmp()[:, 0].numpy(), [cost, cost], rtol=1e-5)
+
+
+def _battery_grid():
+    """Two nodes, one line, two periods: a cheap generator at node 0, a dear
+    one, a load and a battery (charge efficiency 0.9, discharge cost 1) at
+    node 1.  The load peaks in the second period, when the line is
+    congested, so the battery charges in the first and discharges in the
+    second."""
+    f = lambda v: np.asarray(v, dtype=np.float64)
+    return synth.Instance(
+        name="battery2", N=2, T=2, K=0,
+        line_from=np.array([0], np.int32), line_to=np.array([1], np.int32),
+        line_sus=f([4.0]), line_cap=f([1.8]), outage=np.zeros(0, np.int32),
+        gen_node=np.array([0, 1], np.int32), gen_c2=f([0.05, 0.5]), gen_c1=f([10.0, 30.0]),
+        gen_pmin=np.zeros((2, 2)), gen_pmax=f([[4.0, 4.0], [5.0, 5.0]]), gen_ramp=np.zeros(2),
+        load_node=np.array([1], np.int32), load_d=f([[1.0, 3.0]]),
+        bat_node=np.array([1], np.int32), bat_P=f([0.6]), bat_dur=f([2.0]), bat_eta=f([0.9]),
+        bat_alpha=f([1.0]), meta={})
+
+
+def _battery_qp(inst):
+    """The two-node, two-period problem as an exact QP over x = (g0_1, g0_2,
+    g1_1, g1_2, c_1, c_2, delta_1, delta_2): generator cost plus the
+    battery's discharge cost alpha (delta_1 + delta_2) (Section 2.1),
+    balance at node 1 in each period (the line carries g0_t), the state of
+    charge s_2 = eta c_1 - delta_1 within [0, dur P] and back to zero at the
+    end, every box, and the line capacity folded into g0's bounds."""
+    c2, c1 = np.asarray(inst.gen_c2), np.asarray(inst.gen_c1)
+    eta, alpha = float(inst.bat_eta[0]), float(inst.bat_alpha[0])
+    P, smax = float(inst.bat_P[0]), float(inst.bat_dur[0] * inst.bat_P[0])
+    cap, d = float(inst.line_cap[0]), np.asarray(inst.load_d)[0]
+    H = np.diag([2 * c2[0], 2 * c2[0], 2 * c2[1], 2 * c2[1], 0, 0, 0, 0])
+    f = np.array([c1[0], c1[0], c1[1], c1[1], 0, 0, alpha, alpha])
+    E = np.array([[1, 0, 1, 0, -1, 0, 1, 0],
+                  [0, 1, 0, 1, 0, -1, 0, 1],
+                  [0, 0, 0, 0, eta, eta, -1, -1]], float)
+    e = np.array([d[0], d[1], 0.0])
+    C = np.vstack([np.eye(8), [[0, 0, 0, 0, eta, 0, -1, 0]]])
+    pm = np.asarray(inst.gen_pmax)
+    lo = np.array([0, 0, 0, 0, 0, 0, 0, 0, 0], float)
+    hi = np.array([min(pm[0, 0], cap), min(pm[0, 1], cap), pm[1, 0], pm[1, 1], P, P, P, P, smax])
+    x = solve_qp_enum(H, f, E, e, C, lo, hi)
+    return x, float(0.5 * x @ H @ x + f @ x)
+
+
+def test_battery_dispatch_and_cost_match_exact_qp():
+    """A converged solve with a battery in use: the dispatch, the battery's
+    charge and discharge and the objective, which includes alpha * sum(delta),
+    equal the exact QP.  Costing the charge instead of the discharge, or
+    reading the wrong slice of the battery state, moves the objective by
+    more than the tolerance."""
+    inst = _battery_grid()
+    x, obj = _battery_qp(inst)
+    c, dl = x[4:6], x[6:8]
+    assert dl[1] > 0.1 and c[0] > 0.1          # the battery cycles
+    assert abs(float(inst.bat_alpha[0]) * (dl.sum() - c.sum())) > 1e-3 * abs(obj)
+    s = Solver(inst, Options(eps=1e-10, eps_relative=False, max_iter=400000))
+    r = s.solve()
+    assert r.converged
+    assert abs(r.objective - obj) <= 1e-6 * abs(obj)
+    np.testing.assert_allclose(s.dispatch()[:2].numpy().ravel(), x[:4], atol=1e-6)
+    np.testing.assert_allclose(s.dispatch()[3].numpy(), dl - c, atol=1e-6)
+    np.testing.assert_allclose(s.bat.delta[0].numpy(), dl, atol=1e-6)

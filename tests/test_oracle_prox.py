@@ -206,7 +206,7 @@ def _battery_exact(P, dur, eta, alpha, rho_hat, X):
     lo = np.zeros(2 * T + T - 1)
     hi = np.concatenate([P * np.ones(2 * T), dur * P * np.ones(T - 1)])
     x = solve_qp_enum(H, f, E, np.zeros(1), C, lo, hi)
-    return x[T:] - x[:T]
+    return x[:T], x[T:]
 
 
 @pytest.mark.parametrize("T", [1, 2, 3])
@@ -222,9 +222,17 @@ def test_battery_prox_converges_to_exact(T):
     prox = BatteryProx(torch.tensor(P), torch.tensor(dur), torch.tensor(eta),
                        torch.tensor(alpha), T)
     got = prox(torch.tensor(X), rho_hat, rho_hat, 8000).numpy()
-    ref = np.stack([_battery_exact(P[i], dur[i], eta[i], alpha[i], rho_hat, X[i])
-                    for i in range(n)])
-    np.testing.assert_allclose(got, ref, atol=1e-8)
+    exact = [_battery_exact(P[i], dur[i], eta[i], alpha[i], rho_hat, X[i]) for i in range(n)]
+    c_ref = np.stack([e[0] for e in exact])
+    d_ref = np.stack([e[1] for e in exact])
+    np.testing.assert_allclose(got, d_ref - c_ref, atol=1e-8)
+    # the discharge itself (the objective costs alpha * sum(delta), Section
+    # 2.1): with alpha > 0 and eta < 1 the split of p into delta - c is
+    # unique, so the oracle's delta must be the exact one, not merely its
+    # difference with c
+    np.testing.assert_allclose(prox.delta.numpy(), d_ref, atol=1e-8)
+    if T > 1:
+        assert np.any(d_ref > 1e-3) and np.any(c_ref > 1e-3)
     if T == 1:
         # a one-step battery can only dissipate: p = delta - c <= 0
         assert np.all(got <= 1e-9)
