@@ -51,7 +51,18 @@ Readings of the paper used here (each also listed in the design notes):
     overrides the base susceptance and capacity in contingency k; a zero
     susceptance takes an AC line out, and a DC link uses only the capacity;
   * a curtailable load is a generator with pmin = -d < pmax = 0 and a
-    linear cost (c2 = 0).
+    linear cost (c2 = 0);
+  * over-relaxation (Section 3.6) keeps the duplicate variables z (per
+    terminal copy) and xi (node-constant) as state: the prox targets are
+    z - u and xi - v, z' = alpha ptilde' + (1 - alpha) z,
+    xi' = alpha thetabar' + (1 - alpha) xi, u' = u + alpha pbar',
+    v' = v + alpha thetatilde'; the dual residuals are rho ||z' - z|| and
+    rho ||xi' - xi|| (the plain ones when alpha = 1, where z = ptilde and
+    xi = thetabar);
+  * a warm start (Section 3.4) replaces the whole iterate, the inner ADMM
+    state of the time-coupled devices and the penalties with those of
+    another run on a network of the same structure, and restarts the
+    iteration count (and so the adaptive-penalty schedule) at zero.
 """
 from __future__ import annotations
 
@@ -78,6 +89,10 @@ class Options:
     min_iter: int = 0
     inner_iters: int = 10
     inner_omega_scale: float = 1.0
+    # over-relaxation (Section 3.6): alpha in [1, 2); explicit_copies keeps the
+    # duplicate variables (z, xi) as state even at alpha = 1
+    alpha: float = 1.0
+    explicit_copies: bool = False
 
 
 def _t(x, dtype=DT):
@@ -360,10 +375,11 @@ class Residual:
 
 
 class Solver:
-    """Runs the message-passing iteration from the all-zero start."""
+    """Runs the message-passing iteration from the all-zero start, or from
+    an iterate exported by another run (init, see export_state)."""
 
     def __init__(self, inst, opt: Optional[Options] = None, load_d=None, line_cap=None,
-                 gen_pmax=None):
+                 gen_pmax=None, init: Optional[Dict] = None):
         self.net = net = Network(inst, load_d=load_d, line_cap=line_cap, gen_pmax=gen_pmax)
         self.opt = opt or Options()
         self.rho_p = float(self.opt.rho_p)
@@ -391,6 +407,52 @@ class Solver:
         scale = net.load_rms if self.opt.eps_relative else 1.0
         self.eps_eff = self.opt.eps * scale
         self.history: List[Residual] = []
+        a = float(self.opt.alpha)
+        if not 1.0 <= a < 2.0:
+            raise ValueError("the relaxation parameter alpha must lie in [1, 2)")
+        self.relaxed = a != 1.0 or self.opt.explicit_copies
+        self.z, self.xi = z(), z()       # duplicate variables (relaxed form only)
+        if init is not None:
+            self.load_state(init)
+
+    # -- warm start (Section 3.4) ---------------------------------------------
+    _STATE = ("p", "th", "u", "v", "pbar", "thbar", "z", "xi")
+
+    def export_state(self) -> Dict:
+        """The whole iterate: per-terminal tensors, the inner ADMM state of
+        ramp generators and batteries, and the penalties (copies)."""
+        out = {k: getattr(self, k).clone() for k in self._STATE}
+        out["rho_p"], out["rho_th"] = self.rho_p, self.rho_th
+        if self.ramp is not None:
+            out["ramp"] = (self.ramp.beta.clone(), self.ramp.lam.clone())
+        if self.bat is not None:
+            out["bat"] = (self.bat.beta.clone(), self.bat.lam.clone(), self.bat.delta.clone())
+        return out
+
+    def load_state(self, st: Dict):
+        """Continues from an exported iterate of a network with the same
+        structure (terminal order, contingency count, horizon and device
+        classes); the problem data may differ.  The iteration count restarts
+        at zero."""
+        for k in self._STATE:
+            if tuple(st[k].shape) != tuple(getattr(self, k).shape):
+                raise ValueError(f"state {k} has shape {tuple(st[k].shape)}, "
+                                 f"this network needs {tuple(getattr(self, k).shape)}")
+            setattr(self, k, st[k].detach().clone().to(DT))
+        self.rho_p, self.rho_th = float(st["rho_p"]), float(st["rho_th"])
+        for name in ("ramp", "bat"):
+            dev = getattr(self, name)
+            if (dev is None) != (st.get(name) is None):
+                raise ValueError(f"{name} devices differ between the state and this network")
+            if dev is not None:
+                parts = st[name]
+                if tuple(parts[0].shape) != tuple(dev.beta.shape):
+                    raise ValueError(f"{name} inner state has another shape")
+                dev.beta, dev.lam = parts[0].clone(), parts[1].clone()
+                if name == "bat":
+                    dev.delta = parts[2].clone()
+        self.iter = 0
+        self.history = []
 
     # -- one iteration ------------------------------------------------------
     def step(self):
@@ -400,10 +462,17 @@ class Solver:
         p, th, u, v = self.p, self.th, self.u, self.v
         pbar, thbar = self.pbar, self.thbar
         ptil = p - pbar
+        a = float(opt.alpha)
 
-        # step 1: contingency prox on the lines, per contingency k
-        x = ptil - u
-        y = thbar - v
+        # step 1: contingency prox on the lines, per contingency k, at the
+        # targets z - u and xi - v (z = ptilde and xi = thetabar in the
+        # message-passing form; explicit copies when relaxed, Section 3.6)
+        if self.relaxed:
+            x = self.z - u
+            y = self.xi - v
+        else:
+            x = ptil - u
+            y = thbar - v
         s, c = net.line_params()
         s, c = s[:, :, None], c[:, :, None]
         p1, p2, th1, th2 = prox_line(x[:, :L], x[:, L:2 * L], y[:, :L], y[:, L:2 * L],
@@ -412,8 +481,12 @@ class Solver:
         # step 2: non-contingency prox with penalty (K+1) rho at the
         # contingency-averaged targets
         rho_hat = Kp * rp
-        X = (p - (pbar + u)).mean(0)[2 * L:]       # p - avg_k(pbar_k + u_k)
-        Y = (thbar - v).mean(0)[2 * L:]            # avg_k(thbar_k - v_k)
+        if self.relaxed:
+            X = x.mean(0)[2 * L:]                  # avg_k(z_k - u_k)
+            Y = y.mean(0)[2 * L:]                  # avg_k(xi_k - v_k)
+        else:
+            X = (p - (pbar + u)).mean(0)[2 * L:]   # p - avg_k(pbar_k + u_k)
+            Y = (thbar - v).mean(0)[2 * L:]        # avg_k(thbar_k - v_k)
         pnc = torch.zeros(net.Jnc, T, dtype=DT)
         G, D = net.G, net.D
         Xg = X[:G]
@@ -441,15 +514,26 @@ class Solver:
         # step 3: averages and scaled price updates
         pbar_new = net.avg(p_new)
         thbar_new = net.avg(th_new)
-        u_new = u + pbar_new
-        v_new = v + (th_new - thbar_new)
+        ptil_new = p_new - pbar_new
+        if self.relaxed:
+            z_new = a * ptil_new + (1.0 - a) * self.z
+            xi_new = a * thbar_new + (1.0 - a) * self.xi
+            u_new = u + a * pbar_new
+            v_new = v + a * (th_new - thbar_new)
+        else:
+            u_new = u + pbar_new
+            v_new = v + (th_new - thbar_new)
 
         # residuals (Section 3.3)
-        ptil_new = p_new - pbar_new
         r_pp = torch.sqrt((pbar_new ** 2).sum())
         r_pt = torch.sqrt(((th_new - thbar_new) ** 2).sum())
-        r_dp = rp * torch.sqrt(((ptil_new - ptil) ** 2).sum())
-        r_dt = rt * torch.sqrt(((thbar_new - thbar) ** 2).sum())
+        if self.relaxed:
+            r_dp = rp * torch.sqrt(((z_new - self.z) ** 2).sum())
+            r_dt = rt * torch.sqrt(((xi_new - self.xi) ** 2).sum())
+            self.z, self.xi = z_new, xi_new
+        else:
+            r_dp = rp * torch.sqrt(((ptil_new - ptil) ** 2).sum())
+            r_dt = rt * torch.sqrt(((thbar_new - thbar) ** 2).sum())
         norm = math.sqrt(2.0 * net.J * T * Kp)
         rms_pri = float(torch.sqrt(r_pp ** 2 + r_pt ** 2)) / norm
         rms_dual = float(torch.sqrt(r_dp ** 2 + r_dt ** 2)) / norm

@@ -38,20 +38,24 @@ class _Unrolled(torch.autograd.Function):
         power = solver.field_device("PNC").clone()
         obj = torch.tensor(res["objective"], dtype=torch.float64, device=power.device)
         ctx.solver = solver
-        ctx.shapes = (load_d.shape, line_cap.shape, gen_pmax.shape)
+        # each gradient goes back on its input's device, in its dtype and shape
+        ctx.like = [(x.shape, x.dtype, x.device) for x in (load_d, line_cap, gen_pmax)]
         return power, obj
 
     @staticmethod
     def backward(ctx, g_power, g_obj):
         solver = ctx.solver
-        cot = None if g_power is None else g_power.contiguous()
+        if solver is None:
+            raise RuntimeError("unrolled_dispatch: backward ran twice; the recorded run is "
+                               "released after the first backward (retain_graph is not supported)")
+        cot = None if g_power is None else g_power.to(solver.device, torch.float64).contiguous()
         w = 0.0 if g_obj is None else float(g_obj)
         grads = solver.adjoint(cot, w)
         solver.close()
         ctx.solver = None
-        dl, dc, dp = ctx.shapes
-        return (grads["load"].reshape(dl), grads["cap"].reshape(dc), grads["pmax"].reshape(dp),
-                None, None, None, None, None)
+        out = [grads[k].reshape(shape).to(device=dev, dtype=dt)
+               for k, (shape, dt, dev) in zip(("load", "cap", "pmax"), ctx.like)]
+        return (*out, None, None, None, None, None)
 
 
 def unrolled_dispatch(inst, load_d: torch.Tensor, line_cap: torch.Tensor,

@@ -720,6 +720,12 @@ __device__ void finalize_body(const KArgs<R, VT>& a, int n_sweep, int n_nc) {
   double su = 1.0, sv = 1.0;
   int conv = 0, bad = 0;
   if (check) {
+    // a NaN or infinite partial (an overflowed or NaN iterate) is a numeric
+    // failure; it must be caught before the fmax clamps below, which would
+    // turn a NaN into 0
+    bool parts_ok = true;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) parts_ok = parts_ok && isfinite(s[k]);
     // ||ptilde' - ptilde||^2 = sum over terminal copies of dp^2 - sum |n| dpbar^2
     const double pp = fmax(s[0], 0.0), pt = fmax(s[1], 0.0);
     const double dp = rp * rp * fmax(s[4] + s[5] - s[2], 0.0);
@@ -737,7 +743,7 @@ __device__ void finalize_body(const KArgs<R, VT>& a, int n_sweep, int n_nc) {
     rec.rho_th = rt;
     rec.iter = iter;
     rec.precision = ctl->precision;
-    bad = !(isfinite(rec.rms_primal) && isfinite(rec.rms_dual));
+    bad = !(parts_ok && isfinite(rec.rms_primal) && isfinite(rec.rms_dual));
     conv = !bad && fmax(rec.rms_primal, rec.rms_dual) <= ctl->eps_eff && iter >= ctl->min_iter;
     rec.converged = conv;
     if (ctl->adapt_every > 0 && iter % ctl->adapt_every == 0 && !bad) {
@@ -908,7 +914,11 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
 // Tiled sweep over the tiles of all instances of a batch (one work list, in
 // instance order).  A workgroup's tiles of one instance are consecutive in
 // its own sequence, so it writes that instance's residual partials once, in
-// its own slot; it zeroes its slot of every instance it did not visit.
+// its own slot.  It zeroes its slot of every instance it does not visit:
+// those before its first tile, between two instances it visits (a small
+// instance can fall entirely inside one stride of its sequence) and after
+// its last tile, so no slot keeps a value from an earlier launch of another
+// grid size.
 template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_tile_batch(BatchTab tab) {
@@ -916,7 +926,7 @@ k_sweep_tile_batch(BatchTab tab) {
   __shared__ double sh[kTileBlock / kWave];
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_tiles);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  int first = -1, cur_i = -1;
+  int cur_i = -1;
   auto flush = [&](int i) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -925,11 +935,18 @@ k_sweep_tile_batch(BatchTab tab) {
       acc[k] = 0.0;
     }
   };
+  // zeroes this workgroup's slot of the instances lo < i < hi
+  auto zero_between = [&](int lo, int hi) {
+    for (int q = threadIdx.x; q < 5 * (hi - lo - 1); q += kTileBlock) {
+      const int i = lo + 1 + q / 5;
+      descs[i].g.part_sweep[5 * blockIdx.x + (q - 5 * (i - lo - 1))] = 0.0;
+    }
+  };
   for (int64_t g = sweep.first; g < sweep.end; g += sweep.step) {
     const int i = find_inst(tab.tile_prefix, tab.n_inst, g);
     if (i != cur_i) {
       if (cur_i >= 0) flush(cur_i);
-      if (first < 0) first = i;
+      zero_between(cur_i, i);
       cur_i = i;
     }
     const KArgs<R, VT>& a = descs[i];
@@ -943,10 +960,7 @@ k_sweep_tile_batch(BatchTab tab) {
     tile_item<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], t, cq, rp, rt, sv, check, acc);
   }
   if (cur_i >= 0) flush(cur_i);
-  for (int q = threadIdx.x; q < 5 * tab.n_inst; q += kTileBlock) {
-    const int i = q / 5;
-    if (first < 0 || i < first || i > cur_i) descs[i].g.part_sweep[5 * blockIdx.x + (q - 5 * i)] = 0.0;
-  }
+  zero_between(cur_i, tab.n_inst);
 }
 
 template <typename R, typename VT>

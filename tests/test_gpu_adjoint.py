@@ -135,6 +135,18 @@ def test_autograd_function_gives_the_adjoint():
     assert rel(scale.grad, (ref["load"] * torch.tensor(np.asarray(inst.load_d))).sum(1)) <= 1e-9
     assert rel(cap.grad, ref["cap"]) <= 1e-9
     assert rel(pmax.grad, ref["pmax"]) <= 1e-9
+    # CPU inputs: gradients come back on the CPU, in the inputs' dtype; a
+    # second backward through the released run is a clear error
+    x = [torch.tensor(np.asarray(inst.load_d, float), requires_grad=True),
+         cap.detach().cpu().float().requires_grad_(),
+         pmax.detach().cpu().requires_grad_()]
+    power, obj = unrolled_dispatch(inst, x[0], x[1], x[2], 60, 20, **opt)
+    loss = obj + (w * power).sum()
+    loss.backward(retain_graph=True)
+    assert x[0].grad.device.type == "cpu" and x[1].grad.dtype == torch.float32
+    assert rel(x[0].grad, ref["load"]) <= 1e-9 and rel(x[2].grad, ref["pmax"]) <= 1e-9
+    with pytest.raises(RuntimeError, match="backward ran twice"):
+        loss.backward()
 
 
 def _diff_forward(inst, scale, cap, n_iters, dtype="f64"):
@@ -208,3 +220,29 @@ def test_diff_workload_against_finite_differences():
     # piecewise-linear map: exact up to rounding unless a clip switches inside +-h
     assert np.median(errs) <= 1e-4
     assert (errs <= 1e-3).mean() >= 0.8
+
+
+def test_fp32_adjoint_on_diff_workload_close_to_fp64():
+    """The differentiation workload as the benchmark runs it (FP32 iterate,
+    1000 unrolled iterations, checkpoints every 50): the FP32 adjoint agrees
+    with the FP64 adjoint (itself checked against the oracle and finite
+    differences above) within FP32_DIFF_BAR relative for every derivative.
+    The two runs take the same penalty decisions and their dispatches agree
+    to about 7e-6; the derivatives differ by about 2.3e-3, the FP32
+    rounding of 1000 reversed iterations (the adjoint arrays are FP32)."""
+    say("[adjoint] diff workload fp32 vs fp64, 1000 iterations")
+    inst = synth.config("diff")
+    w = weights(inst, seed=2024)
+    g64, r64, p64 = gpu_grads(inst, 1000, w, 1.0, dtype="f64", every=50)
+    g32, r32, p32 = gpu_grads(inst, 1000, w, 1.0, dtype="f32", every=50)
+    say(f"  penalties fp64 {r64['rho_p']:.4g}/{r64['rho_theta']:.4g}, "
+        f"fp32 {r32['rho_p']:.4g}/{r32['rho_theta']:.4g}")
+    say(f"  dispatch: fp32 relative error {rel(p32, p64):.2e}")
+    errs = {k: rel(g32[k], g64[k]) for k in g64}
+    say("  " + ", ".join(f"{k}: {v:.2e}" for k, v in errs.items()))
+    assert (r32["rho_p"], r32["rho_theta"]) == (r64["rho_p"], r64["rho_theta"])
+    for k, e in errs.items():
+        assert e <= FP32_DIFF_BAR, (k, e)
+
+
+FP32_DIFF_BAR = 5e-3

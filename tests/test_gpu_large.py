@@ -7,8 +7,14 @@ the oracle's own operators: line prox (Section 4.2) for random
 (contingency, line, period) entries, node averages and prices (Section 3.2
 step 3) for random (contingency, node, period) entries, and the generator,
 ramp-generator, load and battery prox for random devices (the time-coupled
-ones by replaying the oracle's inner ADMM from the zero start).
+ones by replaying the oracle's inner ADMM from the zero start).  Two steps
+are sampled: iteration 1 -> 2 from the zero start, and iteration 20 -> 21
+with the adaptive penalty of Section 3.5 on and an unbalanced start, so that
+penalties change at iterations 10 and 20 and the price and phase-dual
+rescale of iteration 20 is pending.  The residual norms of Section 3.3 are
+checked at full size against FP64 sums over the exported fields.
 """
+import math
 import sys
 
 import numpy as np
@@ -176,3 +182,138 @@ def test_large_residuals_finite_and_consistent(large_run):
     for key in ["primal_p", "primal_theta", "dual_p", "dual_theta", "objective"]:
         assert np.isfinite(r[key])
     assert r["rms_primal"] > 0 and r["rms_dual"] > 0
+
+
+# ---- iteration 20 -> 21 with penalty changes --------------------------------
+
+def _full_norms(s, inst, tb_prev=None):
+    """||pbar||, ||theta tilde|| over all terminal copies and, given the
+    previous thetabar, ||d thetabar|| weighted by node degree, as FP64 sums
+    over the exported fields of the whole iterate (on the GPU)."""
+    dev = torch.device("cuda")
+    N = inst.N
+    lf = torch.as_tensor(np.asarray(inst.line_from, np.int64), device=dev)
+    lt = torch.as_tensor(np.asarray(inst.line_to, np.int64), device=dev)
+    ncn = torch.as_tensor(np.concatenate([inst.gen_node, inst.load_node, inst.bat_node]).astype(np.int64),
+                          device=dev)
+    deg = torch.zeros(N, dtype=torch.float64, device=dev)
+    deg.index_add_(0, torch.cat([lf, lt, ncn]), torch.ones(2 * len(lf) + len(ncn),
+                                                          dtype=torch.float64, device=dev))
+    pb = s.field_device("PBAR")
+    pp = float((deg[None, :, None] * pb * pb).sum())
+    del pb
+    tb = s.field_device("THBAR")
+    th1 = s.field_device("TH1")
+    pt = float(((th1 - tb[:, lf, :]) ** 2).sum())
+    del th1
+    th2 = s.field_device("TH2")
+    pt += float(((th2 - tb[:, lt, :]) ** 2).sum())
+    del th2
+    thnc = s.field_device("THNC")
+    pt += float(((thnc[None] - tb[:, ncn, :]) ** 2).sum())
+    dt = None
+    if tb_prev is not None:
+        dt = float((deg[None, :, None] * (tb - tb_prev) ** 2).sum())
+    return math.sqrt(pp), math.sqrt(pt), (None if dt is None else math.sqrt(dt)), tb
+
+
+@pytest.fixture(scope="module")
+def large_adaptive():
+    from paper_2410_17203_amd.binding import Solver
+    say("[large] adaptive run to iteration 20")
+    inst = synth.config("large")
+    s = Solver(inst, dtype="f32", polish_fp64=0, eps=0.0, min_iter=2**31 - 1,
+               max_iter=2**31 - 1, rho_p=0.2, rho_theta=5.0, adapt_every=10)
+    rng = np.random.default_rng(321)
+    Kp, L, N, T = inst.K + 1, inst.L, inst.N, inst.T
+    ns = 3000
+    ko = rng.integers(1, Kp, 200)
+    line_idx = tuple(np.concatenate([a, b]) for a, b in
+                     zip((rng.integers(0, Kp, ns), rng.integers(0, L, ns), rng.integers(0, T, ns)),
+                         (ko, inst.outage[ko - 1], rng.integers(0, T, 200))))
+    node_idx = (rng.integers(0, Kp, ns), rng.integers(0, N, ns), rng.integers(0, T, ns))
+    s.iterate(20)
+    r20 = s.residuals()
+    say("[large] norms of iteration 20 from the exported fields")
+    n20 = _full_norms(s, inst)
+    tb20 = n20[3]
+    dev = tb20.device
+    kl, ll, tl = [torch.as_tensor(a, device=dev) for a in line_idx]
+    fr = torch.as_tensor(inst.line_from, device=dev)[ll]
+    to = torch.as_tensor(inst.line_to, device=dev)[ll]
+    smp = {f: s.field_device(f)[kl, ll, tl].cpu() for f in ["P", "TH1", "TH2", "V1", "V2"]}
+    for f in ["U", "PBAR", "THBAR"]:
+        full = s.field_device(f)
+        smp[f + "_f"] = full[kl, fr, tl].cpu()
+        smp[f + "_h"] = full[kl, to, tl].cpu()
+    kn, nn, tn = [torch.as_tensor(a, device=dev) for a in node_idx]
+    u20 = s.field_device("U")[kn, nn, tn].cpu()
+    say("[large] iteration 21")
+    s.iterate(1)
+    r21 = s.residuals()
+    out = {f: s.field_device(f)[kl, ll, tl].cpu() for f in ["P", "TH1", "TH2"]}
+    node_out = {f: s.field_device(f)[kn, nn, tn].cpu() for f in ["PBAR", "U"]}
+    n21 = _full_norms(s, inst, tb20)
+    del tb20
+    s.close()
+    torch.cuda.empty_cache()
+    return dict(inst=inst, line_idx=line_idx, smp=smp, out=out, node_out=node_out, u20=u20,
+                r20=r20, r21=r21, n20=n20[:3], n21=n21[:3])
+
+
+def test_large_penalty_changed_before_the_sampled_step(large_adaptive):
+    d = large_adaptive
+    r20, r21 = d["r20"], d["r21"]
+    assert r20["iter"] == 20 and r21["iter"] == 21
+    # the rule acted after iteration 20: iteration 21 runs with new penalties
+    assert (r21["rho_p"], r21["rho_theta"]) != (r20["rho_p"], r20["rho_theta"])
+
+
+def test_large_line_prox_after_a_penalty_change(large_adaptive):
+    """Iteration 21's line prox from iteration 20's exported iterate (prices
+    and phase duals already rescaled to the new penalties) at the penalties
+    of iteration 21."""
+    d = large_adaptive
+    inst, (k, l, t) = d["inst"], d["line_idx"]
+    smp = d["smp"]
+    alive = np.array([1.0 if (kk == 0 or inst.outage[kk - 1] != ll) else 0.0
+                      for kk, ll in zip(k, l)])
+    s = torch.tensor(inst.line_sus[l] * alive)
+    c = torch.tensor(inst.line_cap[l] * alive)
+    rp, rt = d["r21"]["rho_p"], d["r21"]["rho_theta"]
+    x1 = (-smp["P"] - smp["PBAR_f"]) - smp["U_f"]
+    x2 = (smp["P"] - smp["PBAR_h"]) - smp["U_h"]
+    y1 = smp["THBAR_f"] - smp["V1"]
+    y2 = smp["THBAR_h"] - smp["V2"]
+    _, p2, th1, th2 = prox_line(x1, x2, y1, y2, s, c, rp, rt)
+    scale = max(1.0, float(p2.abs().max()))
+    assert float((d["out"]["P"] - p2).abs().max()) <= TOL * scale
+    tscale = max(1.0, float(th1.abs().max()))
+    assert float((d["out"]["TH1"] - th1).abs().max()) <= TOL * tscale
+    assert float((d["out"]["TH2"] - th2).abs().max()) <= TOL * tscale
+    # a share of the sampled flows sits at the capacity (both clip regimes)
+    assert 0 < int((torch.abs(p2) >= c - 1e-12).logical_and(c > 0).sum()) < len(p2)
+
+
+def test_large_price_update_after_a_penalty_change(large_adaptive):
+    d = large_adaptive
+    no = d["node_out"]
+    u21 = d["u20"].numpy() + no["PBAR"].numpy()
+    assert np.abs(no["U"].numpy() - u21).max() <= TOL * max(1.0, np.abs(u21).max())
+
+
+def test_large_residual_norms_at_full_size(large_adaptive):
+    """The device's FP64 residual norms equal FP64 sums over the exported
+    fields of the whole iterate: rho_theta ||d thetabar|| to summation-order
+    rounding (a sum of squares of differences of the stored FP32 values);
+    ||pbar|| to FP32 rounding, since the exported pbar is W - U of the
+    stored FP32 values while the sweep squares the average it formed before
+    rounding W = U + pbar; ||theta tilde|| to the FP32 rounding of the
+    per-node shifted sums the sweep forms."""
+    d = large_adaptive
+    for r, (pp, pt, dt) in [(d["r20"], d["n20"]), (d["r21"], d["n21"])]:
+        assert abs(r["primal_p"] - pp) <= 1e-6 * pp, (r["iter"], r["primal_p"], pp)
+        assert abs(r["primal_theta"] - pt) <= 1e-4 * pt, (r["iter"], r["primal_theta"], pt)
+        if dt is not None:
+            want = r["rho_theta"] * dt
+            assert abs(r["dual_theta"] - want) <= 1e-9 * want, (r["dual_theta"], want)

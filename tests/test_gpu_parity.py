@@ -1,8 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Iterates are compared field by field after a fixed number of iterations
-(relative L2 error per array: 1e-10 for the FP64 iterate, 1e-4 for FP32),
-residual records iteration by iteration, and converged objectives.  Cases
+(relative L2 error per array: 1e-10 for the FP64 iterate, 1e-4 for FP32,
+and every element on its own, see tests/parity.py), residual records
+iteration by iteration, and converged objectives.  Cases
 span several tiles with ragged tails: K+1 not a multiple of the vector
 width, T below, at and above one wavefront, empty device classes, no-op
 and real outages, zero-capacity lines.
@@ -18,10 +19,9 @@ import torch
 
 from oracle.mp import Options, Solver as Oracle
 from paper_2410_17203_amd import synth
+from tests.parity import BARS, FIELDS, compare_fields as _compare
 
 pytestmark = pytest.mark.gpu
-
-FIELDS = ["P", "TH1", "TH2", "V1", "V2", "U", "PBAR", "THBAR", "PNC", "THNC", "VNC"]
 
 
 def say(msg):
@@ -110,28 +110,20 @@ def rel_err(a, b):
     return na / nb
 
 
-def compare_fields(s, ref, tol, skip=()):
-    worst = {}
-    for f in FIELDS:
-        if f in skip:
-            continue
-        g = s.field(f)
-        r = ref[f].to(torch.float64)
-        assert g.shape == r.shape, (f, g.shape, r.shape)
-        worst[f] = rel_err(g, r)
-    bad = {k: v for k, v in worst.items() if not v <= tol}
-    assert not bad, f"fields beyond {tol}: {bad} (all: {worst})"
-    return worst
+def compare_fields(s, ref, dtype, skip=()):
+    out = _compare(s.field, ref, BARS[dtype], skip=skip)
+    say("  (l2, elementwise) " + ", ".join(f"{k} {v[0]:.1e}/{v[1]:.1e}" for k, v in out.items()))
+    return out
 
 
 @pytest.mark.parametrize("name", ["tiny", "medium", "wide_T", "three_slots", "edge", "no_batteries_T1",
-                                  "curtailable", "hvdc", "changes", "changes_dc"])
+                                  "hub", "curtailable", "hvdc", "changes", "changes_dc"])
 @pytest.mark.parametrize("tiles", [0, 1])
 def test_fp64_iterates_match_oracle(name, tiles):
     say(f"[parity fp64] {name} tiles={tiles}")
     ref, hist = oracle_run(name, 200, 0)
     s = gpu_run(name, 200, "f64", 0, sweep_tiles=tiles)
-    compare_fields(s, ref, 1e-10)
+    compare_fields(s, ref, "f64")
     gh = s.history()
     assert len(gh) == 200
     for a, b in zip(gh, hist):
@@ -155,12 +147,40 @@ def test_fp32_iterates_match_oracle(name, tiles):
     say(f"[parity fp32] {name} tiles={tiles}")
     ref, hist = oracle_run(name, 200, 0)
     s = gpu_run(name, 200, "f32", 0, polish_fp64=0, sweep_tiles=tiles)
-    compare_fields(s, ref, 1e-4)
-    r = s.residuals()
-    b = hist[-1]
-    assert abs(r["primal_p"] - b.primal_p) <= 1e-3 * b.primal_p
-    assert abs(r["objective"] - b.objective) <= 1e-5 * abs(b.objective)
+    compare_fields(s, ref, "f32")
+    # the whole FP32 residual record (the four norms drive the stopping test
+    # and the penalty rule): every iteration within FP32_RESID of the oracle
+    gh = s.history()
+    assert len(gh) == 200
+    worst = {}
+    # the objective starts near zero (generators at their lower limits): its
+    # error is measured against the largest objective of the run
+    obj_scale = max(abs(b.objective) for b in hist) or 1.0
+    for a, b in zip(gh, hist):
+        for key, okey in [("primal_p", "primal_p"), ("primal_theta", "primal_th"),
+                          ("dual_p", "dual_p"), ("dual_theta", "dual_th")]:
+            x, y = a[key], getattr(b, okey)
+            # the dual norms are differences of successive iterates: measured
+            # against the size of the primal power residual of the same
+            # iteration where they fall below it
+            den = max(abs(y), 1e-3 * b.primal_p, 1e-300)
+            worst[key] = max(worst.get(key, 0.0), abs(x - y) / den)
+        worst["objective"] = max(worst.get("objective", 0.0),
+                                 abs(a["objective"] - b.objective) / obj_scale)
+    say("  FP32 residual record, worst relative error: " +
+        ", ".join(f"{k} {v:.1e}" for k, v in worst.items()))
+    bad = {k: v for k, v in worst.items() if not v <= FP32_RESID[k]}
+    assert not bad, (bad, worst)
     s.close()
+
+
+# FP32 residual record against the oracle's: the primal norms are sums of
+# squares of FP32 values (relative error of the 1e-6 level of the iterate);
+# the dual norms are norms of differences of successive iterates, where the
+# iterate's FP32 rounding is amplified by the cancellation; the objective is
+# a sum of FP64 products of FP32 powers.
+FP32_RESID = {"primal_p": 1e-3, "primal_theta": 1e-3, "dual_p": 1e-2, "dual_theta": 1e-2,
+              "objective": 1e-5}
 
 
 def test_adaptive_penalty_sequence_matches_oracle():
@@ -173,7 +193,7 @@ def test_adaptive_penalty_sequence_matches_oracle():
     seq_ora = [(h.rho_p, h.rho_theta) for h in hist]
     assert seq_gpu == pytest.approx(seq_ora, rel=1e-15)
     assert len(set(r[0] for r in seq_ora)) > 2 and len(set(r[1] for r in seq_ora)) > 2
-    compare_fields(s, ref, 1e-10)
+    compare_fields(s, ref, "f64")
     s.close()
 
 
@@ -224,7 +244,7 @@ def test_fp32_to_fp64_switch_carries_links_and_changes():
     s = Solver(make("changes_dc"), dtype="f32", eps=1e-12, max_iter=200, polish_factor=1e30)
     r = s.solve()
     assert r["iter"] == 200 and r["precision"] == 0
-    compare_fields(s, ref, 1e-4)
+    compare_fields(s, ref, "f32")
     s.close()
 
 

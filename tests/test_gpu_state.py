@@ -80,7 +80,14 @@ def test_export_import_continues_bitwise(split):
 
 def test_warm_start_takes_fewer_iterations():
     """Solve, perturb the loads by a few percent (the next day's forecast),
-    solve again from the previous iterate: fewer iterations than from zero."""
+    solve again from the previous iterate: fewer iterations than from zero.
+    The tolerance is 1e-3: with two line outages and a device at most nodes
+    this grid's feasible set under the shared device phases of Section 2.3
+    is small, and the oracle itself stalls at an RMS residual of 7.8e-5
+    (above the 1e-4 threshold of 3.6e-5) after 30,000 iterations, while it
+    reaches 1e-3 in 1,189.  Two solves stopped at a relative tolerance of
+    1e-3 agree in objective to that order; tests/test_gpu_warm.py checks
+    the same warm and cold solves against the oracle to 1e-9."""
     from paper_2410_17203_amd.binding import Solver
     say("[state] warm start")
     shape = dict(synth.CONFIGS["tiny"])
