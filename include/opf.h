@@ -17,7 +17,8 @@
  *   - device memory is never allocated by the library: the caller passes
  *     one workspace (any device allocation, e.g. a PyTorch tensor) whose
  *     size opf_workspace_size() reports; the library borrows it until
- *     opf_destroy();
+ *     opf_destroy(); the one exception is the fixed 64 MiB array per GPU
+ *     behind opf_load_network_static, part of the library's image;
  *   - all device work is enqueued on the stream given in opf_options and
  *     is asynchronous unless a function says it synchronises;
  *   - a context is not thread-safe; use one context per stream.
@@ -164,6 +165,25 @@ opf_status opf_workspace_size(opf_ctx* ctx, const opf_network* net, size_t* byte
  * stream.  Invalid data returns OPF_E_INVALID and leaves ctx unchanged. */
 opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
                             void* d_workspace, size_t bytes);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * opf_load_network, but the workspace is a fixed array of 64 MiB
+ * (67,108,864 bytes) that the library holds on each GPU it runs on until
+ * the process ends, so the caller allocates nothing.  The call itself
+ * allocates no device or pinned memory (the context's pinned readback
+ * buffers come from opf_create).  Networks whose opf_workspace_size exceeds
+ * 64 MiB return OPF_E_OOM and leave ctx unchanged; invalid data returns
+ * OPF_E_INVALID.  One context per GPU holds the array at a time: a later
+ * opf_load_network_static on the same device, from any context, waits for
+ * the holder's stream, takes the array over and leaves the previous holder
+ * unloaded (its calls then return OPF_E_STATE).  Calls of two contexts on
+ * one GPU that overlap in time race on the array.  The array keeps the
+ * last instance's contents; the load clears what must start at zero.
+ * Zero-copy views (opf_state_layout offsets) are relative to the array and
+ * not usable from the caller's memory.  A later opf_load_network or
+ * opf_load_batch on the context releases the array.  Synchronises. */
+opf_status opf_load_network_static(opf_ctx* ctx, const opf_network* net);
 
 /* Batched form (several independent instances of uneven size in one context;
  * the paper batches scenarios in Section 5.5): the workspace holds all of

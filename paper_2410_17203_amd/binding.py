@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "opf_create": (c_int32, [POINTER(Options), POINTER(c_void_p)]),
         "opf_workspace_size": (c_int32, [P, POINTER(Network), POINTER(c_size_t)]),
         "opf_load_network": (c_int32, [P, POINTER(Network), c_void_p, c_size_t]),
+        "opf_load_network_static": (c_int32, [P, POINTER(Network)]),
         "opf_iterate": (c_int32, [P, c_int32]),
         "opf_solve": (c_int32, [P, POINTER(Resid)]),
         "opf_residuals": (c_int32, [P, POINTER(Resid)]),
@@ -235,7 +236,7 @@ class Solver:
     """
 
     def __init__(self, inst, dtype: str = "f64", dual_dtype: Optional[str] = None,
-                 device: str = "cuda:0", **opts):
+                 device: str = "cuda:0", static_workspace: bool = False, **opts):
         import torch
         if not torch.cuda.is_available():
             raise OpfError("no GPU visible: the HIP library has no CPU path")
@@ -247,15 +248,31 @@ class Solver:
         ctx = c_void_p()
         self._check(self.lib.opf_create(byref(self.opt), byref(ctx)), None)
         self.ctx = ctx
+        self.ws = None
+        self.load(inst, static_workspace)
+
+    def load(self, inst, static_workspace: bool = False):
+        """(Re)loads the context with one network or a batch, resetting the
+        iterate.  static_workspace: use the library's fixed per-device
+        workspace (opf_load_network_static; one network, nothing allocated)
+        instead of a new device tensor."""
+        torch = self.torch
         insts = list(inst) if isinstance(inst, (list, tuple)) else [inst]
-        self.insts = insts
         arrays = [NetworkArrays(x) for x in insts]
         nets = (Network * len(insts))(*[a.net for a in arrays])
         nbytes = c_size_t()
         self._check(self.lib.opf_workspace_size_batch(self.ctx, nets, len(insts), byref(nbytes)))
-        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        self._check(self.lib.opf_load_batch(self.ctx, nets, len(insts),
-                                            c_void_p(self.ws.data_ptr()), nbytes))
+        if static_workspace:
+            if len(insts) != 1:
+                raise OpfError("the fixed workspace holds one instance, not a batch")
+            self._check(self.lib.opf_load_network_static(self.ctx, nets))
+            self.ws = None
+        else:
+            ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self._check(self.lib.opf_load_batch(self.ctx, nets, len(insts),
+                                                c_void_p(ws.data_ptr()), nbytes))
+            self.ws = ws
+        self.insts = insts
         self.workspace_bytes = int(nbytes.value)
         self.shapes = [dict(N=int(x.N), T=int(x.T), K=int(x.K), L=len(x.line_from),
                             Jnc=len(x.gen_node) + len(x.load_node) + len(x.bat_node))
@@ -329,6 +346,8 @@ class Solver:
         Tz [T, Zc] (lines taken out by changes);
         device arrays [Jnc, T]."""
         torch = self.torch
+        if self.ws is None:
+            raise OpfError("zero-copy views need a caller workspace, not the fixed one")
         lay = self.layout(instance)
         dt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
         is_dual = name in ("V1", "V2")

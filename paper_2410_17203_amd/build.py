@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libopf.so")
-SOURCES = ["opf_kernels.hip", "opf_adjoint.hip", "opf_host.cpp"]
+SOURCES = ["opf_kernels.hip", "opf_adjoint.hip", "opf_static.hip", "opf_host.cpp"]
 HEADERS = ["opf_internal.h", "opf_device.h", os.path.join("..", "..", "include", "opf.h")]
 
 # Packed FP32 instructions are disabled for all device code: the compiler

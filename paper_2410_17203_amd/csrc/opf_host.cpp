@@ -132,6 +132,11 @@ struct opf_ctx {
   bool bf16_duals = false;
   int64_t host_iter = 0;
   int max_T = 1;
+  // the fixed per-device workspace (opf_load_network_static): the device
+  // whose array holds this context's instance, or -1; taken_over is set when
+  // another context's static load replaced it
+  int static_dev = -1;
+  bool taken_over = false;
   // batch work lists (device) and their descriptors per precision
   BatchTab tab64{}, tab32{};
   void* d_descs64 = nullptr;
@@ -180,6 +185,12 @@ opf_status fail(opf_ctx* c, opf_status s, const std::string& msg) {
   } while (0)
 
 bool finite(double x) { return std::isfinite(x); }
+
+std::string not_loaded_msg(const opf_ctx* c) {
+  return c->taken_over ? "no network loaded: another context's opf_load_network_static took over "
+                         "this device's fixed workspace"
+                       : "no network loaded";
+}
 
 // Validates one network against the context's options.
 opf_status validate(opf_ctx* c, const opf_network* n) {
@@ -1115,7 +1126,7 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
 
 opf_status check_inst(opf_ctx* c, int32_t i) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   if (i < 0 || i >= int(c->inst.size())) return fail(c, OPF_E_INVALID, "instance out of range");
   return OPF_OK;
 }
@@ -1325,7 +1336,7 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
 
 opf_status tape_check(opf_ctx* c) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   if (c->batch) return fail(c, OPF_E_INVALID, "the adjoint supports one instance, not a batch");
   if (c->bf16_duals) return fail(c, OPF_E_INVALID, "the adjoint needs FP32 or FP64 duals, not BF16");
   if (c->opt.inner_iters > kMaxAdjInner)
@@ -1490,9 +1501,18 @@ opf_status state_copy(opf_ctx* c, const Inst& s, int cur, char* blob, bool to_bl
   return OPF_OK;
 }
 
+// Forgets this context's hold on its device's fixed workspace (a load into
+// a caller workspace, or destroy).
+void release_static(opf_ctx* c) {
+  if (c && c->static_dev >= 0) {
+    static_workspace_release(c->static_dev, c);
+    c->static_dev = -1;
+  }
+}
+
 opf_status state_check(opf_ctx* c) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   if (c->batch) return fail(c, OPF_E_INVALID, "state export/import is per single instance");
   if (c->bf16_duals) return fail(c, OPF_E_INVALID, "state export/import needs FP32 or FP64 duals");
   return OPF_OK;
@@ -1557,6 +1577,22 @@ opf_status opf_create(const opf_options* opt, opf_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(o.hip_stream);
   c->bf16_duals = o.dual_dtype == OPF_BF16;
   c->tile_mode = o.sweep_tiles;
+  // set-up that later calls rely on to allocate nothing: the pinned readback
+  // buffers of one instance, and the device address of this device's fixed
+  // workspace.  Without a usable GPU both are left for later (the host-only
+  // calls, e.g. opf_workspace_size, still work).
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    (void)static_workspace_setup(dev);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctl), sizeof(Ctl)) == hipSuccess)
+      c->h_ctl_count = 1;
+    else
+      c->h_ctl = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_rec), sizeof(Rec) * kRing) != hipSuccess)
+      c->h_rec = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_int), 64) != hipSuccess) c->h_int = nullptr;
+  }
+  (void)hipGetLastError();
   *out = c;
   return OPF_OK;
 }
@@ -1571,12 +1607,48 @@ opf_status opf_workspace_size_batch(opf_ctx* c, const opf_network* nets, int32_t
 }
 
 opf_status opf_load_network(opf_ctx* c, const opf_network* n, void* d_ws, size_t bytes) {
+  release_static(c);
   return load(c, n, 1, d_ws, bytes);
 }
 
 opf_status opf_load_batch(opf_ctx* c, const opf_network* nets, int32_t count, void* d_ws,
                           size_t bytes) {
+  release_static(c);
   return load(c, nets, count, d_ws, bytes);
+}
+
+opf_status opf_load_network_static(opf_ctx* c, const opf_network* n) {
+  if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  // the device address of this device's array (taken once, at opf_create or
+  // on the first call on the device)
+  HIP_TRY(c, static_workspace_setup(dev));
+  void* ws = static_workspace(dev);
+  if (!ws) return fail(c, OPF_E_HIP, "no device address for the fixed workspace");
+  if (!c->h_ctl || c->h_ctl_count < 1 || !c->h_rec || !c->h_int)
+    return fail(c, OPF_E_STATE, "the context's pinned readback buffers are missing (opf_create "
+                                "ran without a usable GPU)");
+  size_t need = 0;
+  opf_status st = workspace_size(c, n, 1, &need);
+  if (st != OPF_OK) return st;
+  if (need > kStaticWorkspaceBytes)
+    return fail(c, OPF_E_OOM, "network needs a " + std::to_string(need) +
+                                  "-byte workspace; the fixed workspace holds " +
+                                  std::to_string(kStaticWorkspaceBytes) + " bytes");
+  const void* prev = static_workspace_claim(dev, c);
+  if (prev && prev != c) {
+    // the previous holder's work is finished before its iterate is replaced;
+    // it can no longer be used until it loads again
+    opf_ctx* p = const_cast<opf_ctx*>(static_cast<const opf_ctx*>(prev));
+    (void)hipStreamSynchronize(p->stream);
+    p->loaded = false;
+    p->taken_over = true;
+    p->static_dev = -1;
+  }
+  c->static_dev = dev;
+  c->taken_over = false;
+  return load(c, n, 1, ws, kStaticWorkspaceBytes);
 }
 
 opf_status opf_num_instances(opf_ctx* c, int32_t* count) {
@@ -1587,13 +1659,13 @@ opf_status opf_num_instances(opf_ctx* c, int32_t* count) {
 
 opf_status opf_reset(opf_ctx* c) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   return reset_state(c);
 }
 
 opf_status opf_iterate(opf_ctx* c, int32_t n) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   if (n < 0) return fail(c, OPF_E_INVALID, "n_iters must be >= 0");
   enqueue_n(c, n, false, c->host_iter);
   c->host_iter += n;
@@ -1603,7 +1675,7 @@ opf_status opf_iterate(opf_ctx* c, int32_t n) {
 
 opf_status opf_solve(opf_ctx* c, opf_resid* out) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   const int blk = c->opt.block_iters;
   const int ae = c->opt.adapt_every;
   // graphs need a capturable (non-null) stream and blocks aligned to the
@@ -1769,7 +1841,7 @@ opf_status opf_kernel_times(opf_ctx* c, double* ms, int64_t* launches) {
 
 opf_status opf_kernel_bytes(opf_ctx* c, int32_t kernel, double* bytes) {
   if (!c || !bytes) return fail(c, OPF_E_INVALID, "NULL argument");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   const double S = c->precision == 0 ? 8.0 : 4.0;
   const double SV = c->precision == 0 ? 8.0 : (c->bf16_duals ? 2.0 : 4.0);
   double total = 0.0;
@@ -1801,7 +1873,7 @@ opf_status opf_kernel_bytes(opf_ctx* c, int32_t kernel, double* bytes) {
 
 opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_tuning* out) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
-  if (!c->loaded) return fail(c, OPF_E_STATE, "no network loaded");
+  if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
   if (trials < 1) return fail(c, OPF_E_INVALID, "trials must be >= 1");
   // cache key: device, precision, shape of the loaded instances
   hipDeviceProp_t prop;
@@ -2105,6 +2177,7 @@ const char* opf_last_error(opf_ctx* c) {
 void opf_destroy(opf_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  release_static(c);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);

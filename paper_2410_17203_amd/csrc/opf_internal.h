@@ -317,6 +317,17 @@ template <typename R>
 void launch_adj_cap(const AdjArgs<R>& a, double* grad_cap, hipStream_t s);
 void launch_copy(const CopyList& cl, hipStream_t s);
 
+// Fixed per-device workspace (opf_static.hip) of opf_load_network_static.
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+// Takes the array's device address for `device` (once; later calls return
+// at once).  Must run before static_workspace(device) returns non-null.
+hipError_t static_workspace_setup(int device);
+void* static_workspace(int device);
+// Records owner as the context whose iterate lives in the device's array and
+// returns the previous one (nullptr if none); release forgets owner.
+const void* static_workspace_claim(int device, const void* owner);
+void static_workspace_release(int device, const void* owner);
+
 // Widening copy of a FP32 iterate into a FP64 iterate (polishing).
 template <typename VT>
 void launch_widen(const KArgs<float, VT>& src, const KArgs<double, double>& dst, hipStream_t s);
