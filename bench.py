@@ -99,6 +99,49 @@ def batched_rates(iters, dtype, dual_dtype):
             "algorithmic_elements_per_iteration": elems}
 
 
+def batched_time_to_tolerance(max_iter):
+    """Wall-clock to eq. converge at 1e-3 (relative) of the 64 uneven
+    instances: one batched solve (FP32 iterate, graph blocks, each instance
+    stopping on its own) against the same instances solved one after
+    another with the same arithmetic (FP32 iterate, no FP64 polish, which
+    batches do not apply), so each instance stops at the same iteration
+    either way."""
+    import torch
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import Solver
+    insts = synth.batched()
+    b = Solver(insts, dtype="f32", eps=1e-3, max_iter=max_iter)
+    b.solve()  # warm-up: builds the graphs
+    b.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.solve()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    res = [b.residuals(i) for i in range(len(insts))]
+    b.close()
+    conv_b = [r["converged"] for r in res]
+    iters_b = [r["iter"] for r in res]
+    t_single, conv_s, iters_s = 0.0, [], []
+    for inst in insts:
+        s = Solver(inst, dtype="f32", eps=1e-3, max_iter=max_iter, polish_fp64=0)
+        s.solve()
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t0
+        conv_s.append(r["status"] == "OPF_OK")
+        iters_s.append(r["iter"])
+        s.close()
+    return {"instances": len(insts), "eps": 1e-3, "max_iter": max_iter,
+            "batched_s": t_batch, "one_at_a_time_s": t_single, "speedup": t_single / t_batch,
+            "batched_converged": int(sum(conv_b)), "one_at_a_time_converged": int(sum(conv_s)),
+            "batched_iters_max": int(max(iters_b)), "batched_iters_median": float(sorted(iters_b)[len(iters_b) // 2]),
+            "one_at_a_time_iters_total": int(sum(iters_s))}
+
+
 def general_model_rate(inst, steps, warmup):
     """Iterations/s of the FP32 iterate on the same workload extended to the
     general line model: 3 HVDC links (the paper's network has 3 among about
@@ -154,26 +197,66 @@ def adjoint_times(n_iters, every, dtype):
             "backward_over_forward": (t2 - t1) / (t4 - t3)}
 
 
-def cpu_baseline(inst_name, sample_k, iters):
-    """FP64 oracle on the host: the Large grid with sample_k contingencies,
-    per-iteration time scaled linearly to the full K + 1."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(inst, iters, threads):
+    """Seconds per iteration of the FP64 oracle at the given thread count
+    (one untimed iteration first: it builds the factorisations)."""
     import torch
     from oracle.mp import Options, Solver as Oracle
+    old = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        o = Oracle(inst, Options(eps=1e-12))
+        o.step()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            o.step()
+        return (time.perf_counter() - t0) / iters
+    finally:
+        torch.set_num_threads(old)
+
+
+def cpu_baseline(inst_name, sample_k, iters, medium_iters):
+    """FP64 oracle on the host cores.  The headline figure: the workload's
+    grid and horizon with sample_k contingencies, per-iteration time scaled
+    linearly to the full K + 1 (the oracle's work is linear in K + 1), at
+    all threads torch uses; the same sample at one thread; and the Medium
+    workload run whole (no extrapolation) at all threads."""
+    import torch
     from paper_2410_17203_amd import synth
     full = synth.CONFIGS[inst_name]
+    threads = torch.get_num_threads()
     inst = synth.config(inst_name, K=sample_k)
-    o = Oracle(inst, Options(eps=1e-12))
-    o.step()  # first iteration builds factorisations
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        o.step()
-    dt = (time.perf_counter() - t0) / iters
     scale = (full["K"] + 1) / (sample_k + 1)
-    return {"value": 1.0 / (dt * scale), "unit": "iter/s", "cores": torch.get_num_threads(),
+    dt = _oracle_rate(inst, iters, threads)
+    dt1 = _oracle_rate(inst, max(2, iters // 4), 1)
+    med = synth.config("medium")
+    dtm = _oracle_rate(med, medium_iters, threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": 1.0 / (dt * scale), "unit": "iter/s", "cores": threads,
             "kind": "oracle",
             "sample": (f"{inst_name} grid and horizon with K={sample_k} of {full['K']} "
                        f"contingencies, {iters} timed iterations after 1 untimed; "
-                       f"{dt:.3f} s/iteration scaled by (K+1) ratio {scale:.1f}")}
+                       f"{dt:.3f} s/iteration scaled by the (K+1) ratio {scale:.1f}"),
+            "single_thread_value": 1.0 / (dt1 * scale),
+            "single_thread_sample": f"the same sample, {max(2, iters // 4)} iterations, 1 thread",
+            "medium_full_iters_per_s": 1.0 / dtm,
+            "medium_full_sample": (f"medium workload whole (N=500 L=700 T=24 K=50), "
+                                   f"{medium_iters} iterations, {threads} threads, not scaled"),
+            "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
 
 
 def _read_csv(path):
@@ -285,13 +368,17 @@ def main():
     ap.add_argument("--batched", type=int, default=1,
                     help="1: also time the 64-instance batch against one-at-a-time solves")
     ap.add_argument("--batched-iters", type=int, default=200)
+    ap.add_argument("--batched-ttt", type=int, default=1,
+                    help="1: also time the 64-instance batch to 1e-3 against one-at-a-time solves")
+    ap.add_argument("--batched-ttt-max-iter", type=int, default=4000)
     ap.add_argument("--general", type=int, default=1,
                     help="1: also time the general line model (DC links, per-contingency changes)")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="1: also time 1000 unrolled iterations forward + adjoint (diff workload)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-k", type=int, default=3)
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-medium-iters", type=int, default=40)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="1: first run a plain 1 GiB -> 1 GiB copy kernel three times "
                          "(reference for the HBM byte counters)")
@@ -345,7 +432,12 @@ def main():
     prox = kt["sweep"]
     prox_ms = prox["ms"] / max(prox["launches"], 1)
     prox_bytes = s.kernel_bytes("sweep")
-    achieved = prox_bytes / (prox_ms * 1e-3) / 1e9
+    # algorithmic bytes of the sweep's work: per contingency and period,
+    # every line array read and written (10 L), three of them read again for
+    # the node averages (3 L) and the node arrays (6 N), at S bytes each
+    S = 4 if args.dtype == "f32" else 8
+    alg_bytes = S * (inst.K + 1) * inst.T * (13 * inst.L + 6 * inst.N)
+    achieved = alg_bytes / (prox_ms * 1e-3) / 1e9
     kernel_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()}
     iter_bytes = prox_bytes + s.kernel_bytes("devices")
     log(f"[bench] {value:.2f} it/s; kernel ms/launch {kernel_ms}")
@@ -369,6 +461,23 @@ def main():
         torch.cuda.empty_cache()
 
     # ---- time to tolerance (FP32 with FP64 polish, graph blocks) ----------
+    if args.ttt and args.config == "large":
+        # the same grid and horizon without contingencies: a problem the
+        # reference dispatch certifies feasible under any reading of the
+        # contingency model
+        k0 = synth.config(args.config, K=0)
+        s = Solver(k0, dtype=args.dtype, eps=1e-3, max_iter=args.ttt_max_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        extra["k0_time_to_tol_s"] = time.perf_counter() - t0
+        extra["k0_time_to_tol_iters"] = r["iter"]
+        extra["k0_time_to_tol_converged"] = r["status"] == "OPF_OK"
+        log(f"[bench] K=0 solve: {r['status']} after {r['iter']} it in {extra['k0_time_to_tol_s']:.1f}s")
+        s.close()
+        del s, k0
+        torch.cuda.empty_cache()
     if args.ttt:
         s = Solver(inst, dtype=args.dtype, eps=1e-3, max_iter=args.ttt_max_iter)
         torch.cuda.synchronize()
@@ -425,6 +534,12 @@ def main():
                 f"{b['batched_inst_iters_per_s']:.0f} vs {b['one_at_a_time_inst_iters_per_s']:.0f} "
                 f"instance-iterations/s one at a time")
 
+    if args.batched_ttt:
+        extra["batched_time_to_tol"] = batched_time_to_tolerance(args.batched_ttt_max_iter)
+        b = extra["batched_time_to_tol"]
+        log(f"[bench] batch to 1e-3: {b['batched_s']:.2f}s vs {b['one_at_a_time_s']:.2f}s one at a "
+            f"time; converged {b['batched_converged']}/{b['instances']}")
+
     if args.general:
         extra["general_line_model"] = general_model_rate(inst, 100, 10)
         g = extra["general_line_model"]
@@ -437,6 +552,7 @@ def main():
                 f"(recorded {a['forward_recorded_s']:.3f}s), backward {a['backward_s']:.3f}s")
 
     khash = kernel_source_hash()
+    traffic = traffic_from_profiles(khash, args.dtype)
     out = {
         "metric": METRIC,
         "value": value,
@@ -460,9 +576,17 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": traffic_from_profiles(khash, args.dtype),
-            "algorithmic_bytes_per_launch": prox_bytes,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_model": "S*(K+1)*T*(13L+6N): line arrays read and written, three "
+                                 "re-read for the averages, node arrays",
             "ms_per_launch": prox_ms,
+            "stored_bytes_per_launch": prox_bytes,
+            "stored_model": "S*(K+1)*T*(8L+6N): the arrays this design keeps, read and "
+                            "written once (both phases as one mean, no re-read)",
+            "frac_stored": prox_bytes / (prox_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "frac_counters": (None if traffic is None
+                              else traffic / (prox_ms * 1e-3) / 1e9 / PEAK_HBM_GBS),
         },
         "kernel_ms_per_launch": kernel_ms,
         "iteration_algorithmic_GBps": iter_bytes / (1e-3 / value * 1e3) / 1e9,
@@ -472,7 +596,8 @@ def main():
     out.update(extra)
     if args.cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample_k, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_sample_k, args.cpu_iters,
+                                           args.cpu_medium_iters)
     print(json.dumps(out), flush=True)
 
 

@@ -276,16 +276,23 @@ typedef struct {
   double grid_factor;    /* sweep grid as a multiple of the resident blocks     */
   double ms_per_iter;    /* measured time of one iteration with this choice     */
   int32_t from_cache;    /* 1 if read from cache_path instead of measured       */
-  int32_t tiled;         /* FP32 sweep over node clusters: 1 on, 0 off, -1 by size */
+  int32_t tiled;         /* sweep over node clusters: 1 on, 0 node rows, -1 by size */
+  int32_t tile_groups;   /* period groups per work item of the tiled sweep (a
+                            group is the periods that share one pass: several
+                            where one pass holds all of a period's
+                            contingencies, else one)                         */
 } opf_tuning;
 
 /* Times `trials` iterations for each candidate launch configuration of the
- * loaded instance(s) (lanes per row halved/natural/doubled x sweep grid 0.5/1/2
- * times the resident blocks, and for one instance the tiled sweep on or
- * off), keeps the fastest, and resets the iterate to the zero start.  With
- * cache_path non-NULL, a result for the same device, precision and instance
- * shape is read from that text file instead of being measured, and new
- * results are appended to it.  Synchronises. */
+ * loaded instance(s), for one instance or a batch: the node-row sweep with
+ * lanes per row halved/natural/doubled x sweep grid 0.5/1/2 times the
+ * resident blocks, and, where every instance has clusters, the tiled sweep
+ * with 1, 2 or 4 period groups per work item x grid 0.5/1/2; keeps the
+ * fastest and resets the iterate to the zero start.  With cache_path
+ * non-NULL, a result for the same device, precision and instance shapes is
+ * read from that text file (one line per result: key, lanes shift, grid
+ * factor, tiled, groups, ms) instead of being measured, and new results
+ * are appended to it.  Synchronises. */
 opf_status opf_autotune(opf_ctx* ctx, int32_t trials, const char* cache_path, opf_tuning* out);
 
 /* ---- The iterate: layout, export and import (warm start, Section 3.4) ------ */

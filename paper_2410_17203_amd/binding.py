@@ -82,7 +82,8 @@ class Resid(Structure):
 
 class Tuning(Structure):
     _fields_ = [("lanes_shift", c_int32), ("grid_factor", c_double),
-                ("ms_per_iter", c_double), ("from_cache", c_int32), ("tiled", c_int32)]
+                ("ms_per_iter", c_double), ("from_cache", c_int32), ("tiled", c_int32),
+                ("tile_groups", c_int32)]
 
 
 class Layout(Structure):

@@ -137,13 +137,21 @@ __device__ inline Sweep xcd_sweep(int b, int nb, int64_t n) {
   return s;
 }
 
+// Waits until this wave's LDS operations have completed (lgkmcnt(0); the
+// vector-memory and export counters are left alone; gfx9 encoding).
+__device__ inline void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 // Workgroup barrier that orders LDS accesses only: global loads issued
 // before it stay in flight (a full __syncthreads also waits for every
 // outstanding global load and store of the wave).  For phases that exchange
 // data through LDS and never read back global memory written by the
-// workgroup.
+// workgroup.  The wave's own LDS writes are waited for explicitly before
+// the barrier: the workgroup-scope fence alone let the compiler drop that
+// wait on a loop back-edge, and another wave then read stale LDS after the
+// barrier.
 __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  lds_wait();
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
@@ -159,10 +167,12 @@ __device__ inline double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) sh[w] = v;
+  lds_wait();
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x == 0)
     for (int i = 0; i < NT / kWave; ++i) r += sh[i];
+  lds_wait();
   __syncthreads();
   return r;
 }

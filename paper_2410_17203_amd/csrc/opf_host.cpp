@@ -144,11 +144,13 @@ struct opf_ctx {
   int64_t* d_dev_prefix = nullptr;
   int64_t* d_grp64 = nullptr;
   int64_t* d_grp32 = nullptr;
-  int64_t* d_tiles = nullptr;
+  int64_t* d_tiles64 = nullptr;
+  int64_t* d_tiles32 = nullptr;
   // launch tuning
   int lanes_shift = 0;       // lanes per row = natural value << shift (or >>)
   double grid_factor = 1.0;  // sweep grid = resident blocks * factor
   int tile_mode = -1;        // tiled FP32 sweep: -1 by size, 0 off, 1 on
+  int tile_groups = 1;       // period groups per work item of the tiled sweep
   // pinned readback buffers
   Ctl* h_ctl = nullptr;
   int h_ctl_count = 0;
@@ -375,11 +377,13 @@ void make_geom(const opf_ctx* c, const Inst& s, int vec, int resident, int resid
     g.n_sweep_blocks = std::max(8, std::min(g.n_sweep_blocks, cap));
   }
   g.tile_blocks = 0;
+  g.tile_run = (vec == 2 ? tile_group_periods<double>(s.Kpp) : tile_group_periods<float>(s.Kpp)) *
+               std::max(1, c->tile_groups);
   // the tiled sweep whenever the clusters exist (measured faster than the
   // node rows at every size from 30 nodes up); tile_mode 0 forces node rows
   const bool want_tiles = c->tile_mode != 0;
   if (!c->batch && want_tiles && s.topo.Q > 0 && resident_tile >= 8) {
-    const int64_t items = int64_t(s.T) * s.topo.Q;
+    const int64_t items = int64_t((s.T + g.tile_run - 1) / g.tile_run) * s.topo.Q;
     const int cap = std::min(kMaxSweepBlocks,
                              std::max(8, int(resident_tile * c->grid_factor) / 8 * 8));
     g.tile_blocks = std::max(8, std::min(cap, round8(items)));
@@ -498,7 +502,7 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
 }
 
 struct BatchPlan {
-  size_t descs64, descs32, dev_prefix, grp64, grp32, tiles;
+  size_t descs64, descs32, dev_prefix, grp64, grp32, tiles64, tiles32;
 };
 
 void plan_batch(int count, Layout& L, BatchPlan& b) {
@@ -507,7 +511,8 @@ void plan_batch(int count, Layout& L, BatchPlan& b) {
   b.dev_prefix = L.take(sizeof(int64_t) * (count + 1));
   b.grp64 = L.take(sizeof(int64_t) * (count + 1));
   b.grp32 = L.take(sizeof(int64_t) * (count + 1));
-  b.tiles = L.take(sizeof(int64_t) * (count + 1));
+  b.tiles64 = L.take(sizeof(int64_t) * (count + 1));
+  b.tiles32 = L.take(sizeof(int64_t) * (count + 1));
 }
 
 template <typename R, typename VT>
@@ -690,7 +695,12 @@ opf_status refresh_geometry(opf_ctx* c) {
   }
   if (!c->batch) return OPF_OK;
   const int n = int(c->inst.size());
-  std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0), tiles(n + 1, 0);
+  std::vector<int64_t> dev(n + 1, 0), g64(n + 1, 0), g32(n + 1, 0), tiles64(n + 1, 0),
+      tiles32(n + 1, 0);
+  // estimated work of one tiled-sweep item of each instance (element
+  // updates of a cluster's lines and nodes over the item's periods, plus a
+  // fixed cost), for XCD ranges of equal work
+  std::vector<double> cost64(n), cost32(n);
   // the batch takes the tiled sweep over all instances' tiles when every
   // instance has clusters (unless tile_mode forces node rows)
   bool all_tiles = true;
@@ -702,7 +712,12 @@ opf_status refresh_geometry(opf_ctx* c) {
     dev[i + 1] = dev[i] + s.Jnc;
     g64[i + 1] = g64[i] + s.geom64.n_grps;
     g32[i + 1] = g32[i] + s.geom32.n_grps;
-    tiles[i + 1] = tiles[i] + int64_t(s.T) * s.topo.Q;
+    const int64_t Q = s.topo.Q;
+    tiles64[i + 1] = tiles64[i] + int64_t((s.T + s.geom64.tile_run - 1) / s.geom64.tile_run) * Q;
+    tiles32[i + 1] = tiles32[i] + int64_t((s.T + s.geom32.tile_run - 1) / s.geom32.tile_run) * Q;
+    const double per_period = Q > 0 ? double(2 * s.L + s.N) / double(Q) * s.Kpp : 0.0;
+    cost64[i] = per_period * s.geom64.tile_run + 4096.0;
+    cost32[i] = per_period * s.geom32.tile_run + 4096.0;
     all_tiles = all_tiles && s.topo.Q > 0;
     d64[i] = kargs(s, s.st64, s.geom64);
     d32[i] = kargs(s, s.st32, s.geom32);
@@ -722,12 +737,15 @@ opf_status refresh_geometry(opf_ctx* c) {
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_grp32, g32.data(), sizeof(int64_t) * (n + 1),
                             hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int64_t) * (n + 1),
+  HIP_TRY(c, hipMemcpyAsync(c->d_tiles64, tiles64.data(), sizeof(int64_t) * (n + 1),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_tiles32, tiles32.data(), sizeof(int64_t) * (n + 1),
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const bool want_tiles = all_tiles && c->tile_mode != 0;
   auto tab = [&](BatchTab& t, const void* descs, const int64_t* grp, int64_t total_grps, int res,
-                 int res_tile) {
+                 int res_tile, const int64_t* d_tiles, const std::vector<int64_t>& tiles,
+                 const std::vector<double>& cost) {
     t.descs = descs;
     t.dev_prefix = c->d_dev_prefix;
     t.grp_prefix = grp;
@@ -741,16 +759,34 @@ opf_status refresh_geometry(opf_ctx* c) {
       nb = std::max(8, std::min(nb, std::min(kMaxSweepBlocks,
                                              std::max(8, int(res * c->grid_factor) / 8 * 8))));
     t.n_sweep_blocks = nb;
-    t.tile_prefix = c->d_tiles;
+    t.tile_prefix = d_tiles;
     t.total_tiles = tiles[n];
+    {
+      double total = 0.0;
+      for (int i = 0; i < n; ++i) total += cost[i] * double(tiles[i + 1] - tiles[i]);
+      t.xcd_bounds[0] = 0;
+      int i = 0;
+      double before = 0.0;  // work of the instances before i
+      for (int x = 1; x < 8; ++x) {
+        const double target = total * x / 8.0;
+        while (i < n && before + cost[i] * double(tiles[i + 1] - tiles[i]) < target) {
+          before += cost[i] * double(tiles[i + 1] - tiles[i]);
+          ++i;
+        }
+        int64_t b = tiles[n];
+        if (i < n) b = tiles[i] + int64_t(std::ceil((target - before) / cost[i]));
+        t.xcd_bounds[x] = std::min(tiles[n], std::max(t.xcd_bounds[x - 1], b));
+      }
+      t.xcd_bounds[8] = tiles[n];
+    }
     t.tile_blocks = 0;
     if (want_tiles && res_tile >= 8)
       t.tile_blocks = std::max(8, std::min(std::min(kMaxSweepBlocks,
                                                     std::max(8, int(res_tile * c->grid_factor) / 8 * 8)),
                                            round8(tiles[n])));
   };
-  tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64, tile64);
-  tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32, tile32);
+  tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64, tile64, c->d_tiles64, tiles64, cost64);
+  tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32, tile32, c->d_tiles32, tiles32, cost32);
   return OPF_OK;
 }
 
@@ -1112,7 +1148,8 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
     c->d_dev_prefix = reinterpret_cast<int64_t*>(c->ws + bp.dev_prefix);
     c->d_grp64 = reinterpret_cast<int64_t*>(c->ws + bp.grp64);
     c->d_grp32 = reinterpret_cast<int64_t*>(c->ws + bp.grp32);
-    c->d_tiles = reinterpret_cast<int64_t*>(c->ws + bp.tiles);
+    c->d_tiles64 = reinterpret_cast<int64_t*>(c->ws + bp.tiles64);
+    c->d_tiles32 = reinterpret_cast<int64_t*>(c->ws + bp.tiles32);
   }
   s = refresh_geometry(c);
   if (s != OPF_OK) return s;
@@ -1891,18 +1928,19 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
       << c->inst.size() << "|NT" << sN << "|LT" << sL << "|KT" << sKT;
   opf_tuning best{};
   best.ms_per_iter = 1e300;
+  best.tile_groups = 1;
   bool cached = false;
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string k;
-    int shift;
+    int shift, tiled, groups;
     double gf, ms;
-    int tiled;
-    while (in >> k >> shift >> gf >> tiled >> ms)
+    while (in >> k >> shift >> gf >> tiled >> groups >> ms)
       if (k == key.str()) {
         best.lanes_shift = shift;
         best.grid_factor = gf;
         best.tiled = tiled;
+        best.tile_groups = std::max(1, std::min(8, groups));
         best.ms_per_iter = ms;
         cached = true;
       }
@@ -1913,34 +1951,47 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    const bool tiles_possible = !c->batch && c->inst[0].topo.Q > 0;
-    for (int tm = 0; tm <= (tiles_possible ? 1 : 0); ++tm)
-    for (int shift = -1; shift <= 1; ++shift) {
-      for (double gf : {0.5, 1.0, 2.0}) {
-        if (tm == 1 && shift != 0) continue;  // the tiled sweep has no lane groups
-        c->tile_mode = tiles_possible ? tm : -1;
-        c->lanes_shift = shift;
-        c->grid_factor = gf;
-        opf_status s = refresh_geometry(c);
-        if (s != OPF_OK) return s;
-        s = reset_state(c);
-        if (s != OPF_OK) return s;
-        enqueue_n(c, 2, false, c->host_iter);  // warm-up
-        c->host_iter += 2;
-        HIP_TRY(c, hipEventRecord(e0, c->stream));
-        enqueue_n(c, trials, false, c->host_iter);
-        c->host_iter += trials;
-        HIP_TRY(c, hipEventRecord(e1, c->stream));
-        HIP_TRY(c, hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-        const double per = double(ms) / trials;
-        if (per < best.ms_per_iter) {
-          best.ms_per_iter = per;
-          best.lanes_shift = shift;
-          best.grid_factor = gf;
-          best.tiled = c->tile_mode;
-        }
+    bool tiles_possible = true;  // every instance has clusters
+    for (const Inst& x : c->inst) tiles_possible = tiles_possible && x.topo.Q > 0;
+    // candidates: node rows (lanes per row x grid) and, where the clusters
+    // exist, the tiled sweep (grid x period groups per work item)
+    struct Cand {
+      int tm, shift, groups;
+      double gf;
+    };
+    std::vector<Cand> cands;
+    for (int shift = -1; shift <= 1; ++shift)
+      for (double gf : {0.5, 1.0, 2.0}) cands.push_back({0, shift, 1, gf});
+    if (tiles_possible)
+      for (int groups : {1, 2, 4})
+        for (double gf : {0.5, 1.0, 2.0}) cands.push_back({1, 0, groups, gf});
+    for (const Cand& cd : cands) {
+      const int shift = cd.shift;
+      const double gf = cd.gf;
+      c->tile_mode = cd.tm;
+      c->tile_groups = cd.groups;
+      c->lanes_shift = shift;
+      c->grid_factor = gf;
+      opf_status s = refresh_geometry(c);
+      if (s != OPF_OK) return s;
+      s = reset_state(c);
+      if (s != OPF_OK) return s;
+      enqueue_n(c, 2, false, c->host_iter);  // warm-up
+      c->host_iter += 2;
+      HIP_TRY(c, hipEventRecord(e0, c->stream));
+      enqueue_n(c, trials, false, c->host_iter);
+      c->host_iter += trials;
+      HIP_TRY(c, hipEventRecord(e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+      const double per = double(ms) / trials;
+      if (per < best.ms_per_iter) {
+        best.ms_per_iter = per;
+        best.lanes_shift = shift;
+        best.grid_factor = gf;
+        best.tiled = c->tile_mode;
+        best.tile_groups = cd.groups;
       }
     }
     (void)hipEventDestroy(e0);
@@ -1949,12 +2000,13 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);
       outf << key.str() << " " << best.lanes_shift << " " << best.grid_factor << " "
-           << best.tiled << " " << best.ms_per_iter << "\n";
+           << best.tiled << " " << best.tile_groups << " " << best.ms_per_iter << "\n";
     }
   }
   c->lanes_shift = best.lanes_shift;
   c->grid_factor = best.grid_factor;
   c->tile_mode = best.tiled;
+  c->tile_groups = best.tile_groups;
   opf_status s = refresh_geometry(c);
   if (s != OPF_OK) return s;
   s = reset_state(c);

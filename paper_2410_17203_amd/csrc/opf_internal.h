@@ -51,6 +51,28 @@ constexpr int kTileDev = 128;               // most generators, loads, batteries
 #define OPF_TILE_BLOCK 512
 #endif
 constexpr int kTileBlock = OPF_TILE_BLOCK;  // threads per workgroup of the tiled sweep
+#ifndef OPF_PASS_BYTES
+#define OPF_PASS_BYTES 128
+#endif
+// Contingencies per pass of the tiled sweep: 128 bytes of each row (a chunk
+// in FP32, half a chunk in FP64).
+template <typename R>
+__host__ __device__ constexpr int tile_pass_elems() {
+  return OPF_PASS_BYTES / int(sizeof(R)) < kChunk ? OPF_PASS_BYTES / int(sizeof(R)) : kChunk;
+}
+// Periods that share one pass of the tiled sweep for an instance of Kpp
+// (padded) contingencies: where a pass holds all of a period's
+// contingencies, as many periods as fill it, at most 4 in FP32 (the LDS
+// holds the device values of 4 periods) and 1 in FP64.
+template <typename R>
+__host__ __device__ inline int tile_group_periods(int Kpp) {
+  constexpr int VEC = 16 / int(sizeof(R));
+  constexpr int SUB = tile_pass_elems<R>();
+  constexpr int NPP = sizeof(R) == 4 ? 4 : 1;
+  if (Kpp > SUB) return 1;
+  const int nv = (SUB / VEC) / (Kpp / VEC);
+  return nv < NPP ? nv : NPP;
+}
 
 // Element index of contingency k of item i (a line, count = L, or a node,
 // count = N) in period t.
@@ -177,6 +199,8 @@ struct Geom {
   int64_t n_grps;         // ceil(N*T / rows_per_grp), rows ordered t * N + n
   int32_t n_sweep_blocks; // multiple of 8
   int32_t tile_blocks;    // grid of the tiled sweep (0: node-row sweep is used)
+  int32_t tile_run;       // periods per work item of the tiled sweep (a multiple of
+                          // tile_group_periods; the item's cluster tables are staged once)
   int32_t n_part;         // residual partials written by the active sweep kernel
   int32_t inner_iters;
   double omega_scale;
@@ -204,8 +228,9 @@ struct BatchTab {
   int32_t n_sweep_blocks;
   int32_t any_gen;            // some instance has DC links or per-contingency changes
   int32_t tile_blocks;        // > 0: the tiled sweep over all instances' tiles, with this grid
-  const int64_t* tile_prefix; // [n_inst + 1] prefix of T * Q (tiles) over the instances
+  const int64_t* tile_prefix; // [n_inst + 1] prefix of the work items (runs x clusters)
   int64_t total_tiles;
+  int64_t xcd_bounds[9];      // the work list split into 8 XCD ranges of equal estimated work
   int64_t total_dev;
   int64_t total_grps;
 };

@@ -338,22 +338,28 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 // registers of the thread that owns the node across the chunks.  Tiles of
 // one period follow the node order, so cut lines and far nodes read by one
 // cluster were usually just read by its neighbour on the same XCD.
-// One tile of the sweep: one period t and cluster cq of the instance a,
-// all contingencies pass by pass; adds the tile's FP64 residual partials to
-// acc.  Called by the single-instance and the batched tiled sweeps.
+// One work item of the tiled sweep: cluster cq of the instance a over the
+// periods [t0, t1), all contingencies; adds the item's FP64 residual
+// partials to acc.  Called by the single-instance and the batched tiled
+// sweeps.  The cluster's tables (its lines, terminal lists, device lists,
+// degrees) are staged in LDS once for all the item's periods.  Periods are
+// taken in groups: where one 128-byte pass holds all of a period's
+// contingencies (K+1 <= 32 in FP32), up to tile_group_periods() periods
+// share one pass, so a narrow instance fills the workgroup instead of a
+// fraction of it; otherwise one period at a time, pass by pass.  Each
+// thread's node rows of the next pass (or of the next group's first pass)
+// are loaded while the current pass finishes.
 template <typename R, typename VT, bool GEN>
-__device__ __forceinline__ void tile_item(const KArgs<R, VT>& a, const Buf<R, VT>& A,
-                                          const Buf<R, VT>& B, int t, int cq, R rp, R rt, R sv,
-                                          bool check, double (&acc)[5]) {
+__device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>& A,
+                                         const Buf<R, VT>& B, int cq, int t0, int t1, R rp, R rt,
+                                         R sv, bool check, double (&acc)[5]) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
   // chunk in FP64), so that the LDS footprint is the same in both precisions
-#ifndef OPF_PASS_BYTES
-#define OPF_PASS_BYTES 128
-#endif
-  constexpr int SUB = OPF_PASS_BYTES / int(sizeof(R)) < kChunk ? OPF_PASS_BYTES / int(sizeof(R)) : kChunk;
+  constexpr int SUB = tile_pass_elems<R>();
   constexpr int NVMAX = SUB / VEC;  // vectors per pass row
-  static_assert(NVMAX <= 16 && kTileLines * NVMAX < 4096, "x / nvc by multiply and shift");
+  constexpr int NPP = sizeof(R) == 4 ? 4 : 1;
+  static_assert(NVMAX <= 16 && kTileLines * NVMAX < 4096, "x / nvt by multiply and shift");
   static_assert(kTileNodes * NVMAX <= kTileBlock, "one node vector per thread and pass");
   using VR = Vec<R, VEC>;
   using VV = Vec<VT, VEC>;
@@ -366,13 +372,18 @@ __device__ __forceinline__ void tile_item(const KArgs<R, VT>& a, const Buf<R, VT
   __shared__ __align__(16) R sH[kTileLines * SUB];
   __shared__ R sRw[kTileNodes * NVMAX], sRb[kTileNodes * NVMAX];
   __shared__ int4 sTl[kTileLines];
-  // the cluster's terminal lists for the node sums, staged once per tile:
+  // the cluster's terminal lists for the node sums, staged once per item:
   // line terminals (CSR pointers local to the cluster, entries as in tcsr)
-  // and the devices' power and phase in this period (at most kTileDev: the
-  // clusters are built so)
-  __shared__ int sLp[kTileNodes + 1], sNp[kTileNodes + 1], sTc[2 * kTileLines];
-  __shared__ R sDp[kTileDev], sDt[kTileDev];
-  __shared__ double sDg[kTileNodes], sIdg[kTileNodes];
+  // and its devices (ids, and their power and phase in the group's periods;
+  // at most kTileDev devices: the clusters are built so)
+  __shared__ int sLp[kTileNodes + 1], sNp[kTileNodes + 1], sTc[2 * kTileLines], sJd[kTileDev];
+  __shared__ R sDp[NPP * kTileDev], sDt[NPP * kTileDev];
+  __shared__ float sDg[kTileNodes];  // node degrees (integers, exact)
+  __shared__ double sIdg[kTileNodes];
+  // running FP64 sums over a period's passes of W and thetabar per node
+  // (periods with several passes are taken one at a time), kept by the
+  // node's thread in LDS rather than in registers across the passes
+  __shared__ double sAccW[kTileNodes], sAccB[kTileNodes];
   const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
   const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
   const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
@@ -384,254 +395,290 @@ __device__ __forceinline__ void tile_item(const KArgs<R, VT>& a, const Buf<R, VT
     sLp[i] = tp.node_lptr[n0 + i] - lp0;
     sNp[i] = tp.node_nptr[n0 + i] - np0;
     if (i < cn) {
-      sDg[i] = tp.deg[n0 + i];
+      sDg[i] = float(tp.deg[n0 + i]);
       sIdg[i] = tp.inv_deg[n0 + i];
     }
   }
   for (int q = threadIdx.x; q < nlt; q += kTileBlock) sTc[q] = tp.tcsr[lp0 + q];
-  for (int q = threadIdx.x; q < ndt; q += kTileBlock) {
-    const int jd = tp.node_nterm[np0 + q];
-    sDp[q] = a.st.pnc[size_t(jd) * T + t];
-    sDt[q] = a.st.thnc[size_t(jd) * T + t];
-  }
-  double runW = 0.0, runB = 0.0;  // FP64: up to 1024 contingencies are summed
-  // row sums of the previous pass (prev_nvc vectors per node) wait in sRw,
-  // sRb and are added after the next pass's first barrier
-  int prev_nvc = 0;
-  const R* td_old = A.Td + size_t(t) * Kpp;
-  R* td_new = B.Td + size_t(t) * Kpp;
-  // Each thread owns at most one node vector per pass (phases 0 and 2).
-  // Its W and thetabar rows are loaded one pass ahead (in flight during
-  // the previous pass's phase 2) and its price row before phase 1.
-  // node_vec: offset of this thread's node vector in the pass at s0, or -1.
-  auto node_vec = [&](int s0) -> int64_t {
+  for (int q = threadIdx.x; q < ndt; q += kTileBlock) sJd[q] = tp.node_nterm[np0 + q];
+  const int npp = tile_group_periods<R>(Kpp);
+  // Pass geometry: a pass covers the periods [tg, tg + ng) and the
+  // contingencies [s0, s0 + nvc VEC) of each (one chunk or part of one).
+  // Vector u of a row in the pass is period tg + u / nvc, vector u % nvc.
+  // Each thread owns at most one node vector per pass.
+  auto node_vec = [&](int tg, int ng, int s0) -> int64_t {
     const int c0 = s0 & ~(kChunk - 1);
     const int w = min(kChunk, Kpp - c0);
     const int nvc = min(SUB, c0 + w - s0) / VEC;
-    if (int(threadIdx.x) >= cn * nvc) return -1;
-    const int i = int((uint32_t(threadIdx.x) * ((65536u + uint32_t(nvc) - 1u) / uint32_t(nvc))) >> 16);
-    const int v = threadIdx.x - i * nvc;
-    return int64_t((size_t(t) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + i) * w + v * VEC);
+    const int nvt = ng * nvc;
+    if (int(threadIdx.x) >= cn * nvt) return -1;
+    const int i = int((uint32_t(threadIdx.x) * ((65536u + uint32_t(nvt) - 1u) / uint32_t(nvt))) >> 16);
+    const int u = threadIdx.x - i * nvt;
+    const int p = int((uint32_t(u) * ((65536u + uint32_t(nvc) - 1u) / uint32_t(nvc))) >> 16);
+    const int v = u - p * nvc;
+    return int64_t((size_t(tg + p) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + i) * w + v * VEC);
   };
   // (held as native 16-byte vectors so that they stay in registers)
   u32x4 pW = {0u, 0u, 0u, 0u}, pB = {0u, 0u, 0u, 0u};
   {
-    const int64_t o = node_vec(0);
+    const int64_t o = node_vec(t0, min(npp, t1 - t0), 0);
     if (o >= 0) {
       pW = *reinterpret_cast<const u32x4*>(A.W + o);
       pB = *reinterpret_cast<const u32x4*>(A.TB + o);
     }
   }
-  for (int s0 = 0; s0 < Kpp; s0 += SUB) {
-    const int c0 = s0 & ~(kChunk - 1);
-    const int w = min(kChunk, Kpp - c0);                 // chunk width
-    const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors in this pass
-    // x / nvc as a multiply and shift (exact for nvc <= 16, x < 4096)
-    const uint32_t nvc_mag = (65536u + uint32_t(nvc) - 1u) / uint32_t(nvc);
-    // element (item i, vector v) of this pass: base + i * w + v * VEC
-    const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
-    const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
-    const bool own = int(threadIdx.x) < cn * nvc;
-    const int ii = int((uint32_t(threadIdx.x) * nvc_mag) >> 16), vv = threadIdx.x - ii * nvc;
-    lds_barrier();  // sTl written; LDS of the previous chunk no longer read
-    if (threadIdx.x < cn) {
-      for (int v = 0; v < prev_nvc; ++v) {
-        runW += double(sRw[threadIdx.x * prev_nvc + v]);
-        runB += double(sRb[threadIdx.x * prev_nvc + v]);
-      }
-    }
-    u32x4 pU = {0u, 0u, 0u, 0u};
-    if (own) {
-      *reinterpret_cast<u32x4*>(sW + ii * SUB + vv * VEC) = pW;
-      *reinterpret_cast<u32x4*>(sB + ii * SUB + vv * VEC) = pB;
-      pU = __builtin_nontemporal_load(
-          reinterpret_cast<const u32x4*>(A.U + nbase + size_t(n0 + ii) * w + vv * VEC));
-    }
-    lds_barrier();
-    for (int x = threadIdx.x; x < nl * nvc; x += kTileBlock) {
-      const int j = int((uint32_t(x) * nvc_mag) >> 16), v = x - j * nvc;
-      const int4 e = sTl[j];
-      const int l = e.x;
-      const int k0 = s0 + v * VEC;
-      const size_t ol = lbase + size_t(l) * w + v * VEC;
-      const VR P = *reinterpret_cast<const VR*>(A.P + ol);
-      const VR Tm = *reinterpret_cast<const VR*>(A.Tm + ol);
-      const VV V1 = *reinterpret_cast<const VV*>(A.V1 + ol);
-      const VV V2 = *reinterpret_cast<const VV*>(A.V2 + ol);
-      const size_t ofar = nbase + size_t(e.w < 0 ? 0 : e.w) * w + v * VEC;
-      VR Wf, Wh, Bf, Bh;
-      if (e.y >= 0) {
-        Wf = *reinterpret_cast<const VR*>(sW + e.y * SUB + v * VEC);
-        Bf = *reinterpret_cast<const VR*>(sB + e.y * SUB + v * VEC);
-      } else {
-        Wf = *reinterpret_cast<const VR*>(A.W + ofar);
-        Bf = *reinterpret_cast<const VR*>(A.TB + ofar);
-      }
-      if (e.z >= 0) {
-        Wh = *reinterpret_cast<const VR*>(sW + e.z * SUB + v * VEC);
-        Bh = *reinterpret_cast<const VR*>(sB + e.z * SUB + v * VEC);
-      } else {
-        Wh = *reinterpret_cast<const VR*>(A.W + ofar);
-        Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
-      }
-      const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
-      LineOut<R, VEC> o;
-      int dci = -1;
-      size_t oh = 0;
-      LinePar<R, VEC> lp;
-      bool special = false;  // as in the node-row sweep
-      if constexpr (GEN) {
-        dci = tp.line_dc[l];
-        special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
-      }
-      if (special) {
-        oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
-                      : 0;
-        VR Hx{};
-        if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
-        line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
-        line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
-      } else {
-        line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
-                              R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
-      }
-      if (e.y >= 0) {  // the cluster holding the from node stores the line
-        VR Pn, Tn;
-        VV V1n, V2n;
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          Pn.x[q] = o.p[q];
-          Tn.x[q] = o.tm[q];
-          V1n.x[q] = DIO<VT, R>::out(o.v1[q]);
-          V2n.x[q] = DIO<VT, R>::out(o.v2[q]);
-          if (ok.x[q] == l) td_new[k0 + q] = o.half[q];
-          if (check) {
-            const double dp = double(o.p[q]) - double(P.x[q]);
-            acc[4] += 2.0 * dp * dp;
+  for (int tg = t0; tg < t1; tg += npp) {
+    const int ng = min(npp, t1 - tg);  // periods in this group
+    // row sums of the previous pass (ng * prev_nvc vectors per node) wait in
+    // sRw, sRb; with several passes per period (then ng = 1) they are added
+    // to sAccW, sAccB after the next pass's first barrier (FP64: up to 1024
+    // contingencies are summed for the step-2 means)
+    int prev_nvc = 0;
+    for (int s0 = 0; s0 < Kpp; s0 += SUB) {
+      const int c0 = s0 & ~(kChunk - 1);
+      const int w = min(kChunk, Kpp - c0);                 // chunk width
+      const int nvc = min(SUB, c0 + w - s0) / VEC;         // vectors per period in this pass
+      const int nvt = ng * nvc;                            // vectors per row in this pass
+      // x / nvt and u / nvc as a multiply and shift (exact for divisors <= 16, x < 4096)
+      const uint32_t nvt_mag = (65536u + uint32_t(nvt) - 1u) / uint32_t(nvt);
+      const uint32_t nvc_mag = (65536u + uint32_t(nvc) - 1u) / uint32_t(nvc);
+      const bool own = int(threadIdx.x) < cn * nvt;
+      const int ii = int((uint32_t(threadIdx.x) * nvt_mag) >> 16), uu = threadIdx.x - ii * nvt;
+      const int pp = int((uint32_t(uu) * nvc_mag) >> 16), vv = uu - pp * nvc;
+      lds_barrier();  // the previous pass's LDS is no longer read
+      if (int(threadIdx.x) < cn) {  // (only this thread touches its node's entries)
+        double aw = 0.0, ab = 0.0;
+        if (prev_nvc > 0) {
+          aw = sAccW[threadIdx.x];
+          ab = sAccB[threadIdx.x];
+          for (int v = 0; v < prev_nvc; ++v) {
+            aw += double(sRw[threadIdx.x * prev_nvc + v]);
+            ab += double(sRb[threadIdx.x * prev_nvc + v]);
           }
         }
-        st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
-        st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
-        st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
-        st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+        sAccW[threadIdx.x] = aw;
+        sAccB[threadIdx.x] = ab;
+      }
+      if (s0 == 0) {  // device powers and phases of the group's periods
+        for (int q = threadIdx.x; q < ndt * ng; q += kTileBlock) {
+          const int p = q / ndt, d = q - p * ndt;
+          const size_t o = size_t(sJd[d]) * T + tg + p;
+          sDp[p * kTileDev + d] = a.st.pnc[o];
+          sDt[p * kTileDev + d] = a.st.thnc[o];
+        }
+      }
+      u32x4 pU = {0u, 0u, 0u, 0u};
+      if (own) {
+        *reinterpret_cast<u32x4*>(sW + ii * SUB + uu * VEC) = pW;
+        *reinterpret_cast<u32x4*>(sB + ii * SUB + uu * VEC) = pB;
+        const size_t on = (size_t(tg + pp) * Kpp + c0) * N + (s0 - c0) + size_t(n0 + ii) * w +
+                          vv * VEC;
+        pU = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(A.U + on));
+      }
+      lds_barrier();
+      for (int x = threadIdx.x; x < nl * nvt; x += kTileBlock) {
+        const int j = int((uint32_t(x) * nvt_mag) >> 16), u = x - j * nvt;
+        const int p = int((uint32_t(u) * nvc_mag) >> 16), v = u - p * nvc;
+        const int t = tg + p;
+        const size_t nbase = (size_t(t) * Kpp + c0) * N + (s0 - c0);
+        const size_t lbase = (size_t(t) * Kpp + c0) * L + (s0 - c0);
+        const R* td_old = A.Td + size_t(t) * Kpp;
+        R* td_new = B.Td + size_t(t) * Kpp;
+        const int4 e = sTl[j];
+        const int l = e.x;
+        const int k0 = s0 + v * VEC;
+        const size_t ol = lbase + size_t(l) * w + v * VEC;
+        const VR P = *reinterpret_cast<const VR*>(A.P + ol);
+        const VR Tm = *reinterpret_cast<const VR*>(A.Tm + ol);
+        const VV V1 = *reinterpret_cast<const VV*>(A.V1 + ol);
+        const VV V2 = *reinterpret_cast<const VV*>(A.V2 + ol);
+        const size_t ofar = nbase + size_t(e.w < 0 ? 0 : e.w) * w + v * VEC;
+        VR Wf, Wh, Bf, Bh;
+        if (e.y >= 0) {
+          Wf = *reinterpret_cast<const VR*>(sW + e.y * SUB + u * VEC);
+          Bf = *reinterpret_cast<const VR*>(sB + e.y * SUB + u * VEC);
+        } else {
+          Wf = *reinterpret_cast<const VR*>(A.W + ofar);
+          Bf = *reinterpret_cast<const VR*>(A.TB + ofar);
+        }
+        if (e.z >= 0) {
+          Wh = *reinterpret_cast<const VR*>(sW + e.z * SUB + u * VEC);
+          Bh = *reinterpret_cast<const VR*>(sB + e.z * SUB + u * VEC);
+        } else {
+          Wh = *reinterpret_cast<const VR*>(A.W + ofar);
+          Bh = *reinterpret_cast<const VR*>(A.TB + ofar);
+        }
+        const VI ok = *reinterpret_cast<const VI*>(tp.outage_k + k0);
+        LineOut<R, VEC> o;
+        int dci = -1;
+        size_t oh = 0;
+        LinePar<R, VEC> lp;
+        bool special = false;  // as in the node-row sweep
+        if constexpr (GEN) {
+          dci = tp.line_dc[l];
+          special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
+        }
         if (special) {
-          if (dci >= 0) {
-            VR Hn;
+          oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
+                        : 0;
+          VR Hx{};
+          if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
+          line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
+          line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
+        } else {
+          line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
+                                R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
+        }
+        if (e.y >= 0) {  // the cluster holding the from node stores the line
+          VR Pn, Tn;
+          VV V1n, V2n;
 #pragma unroll
-            for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
-            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+          for (int q = 0; q < VEC; ++q) {
+            Pn.x[q] = o.p[q];
+            Tn.x[q] = o.tm[q];
+            V1n.x[q] = DIO<VT, R>::out(o.v1[q]);
+            V2n.x[q] = DIO<VT, R>::out(o.v2[q]);
+            if (ok.x[q] == l) td_new[k0 + q] = o.half[q];
+            if (check) {
+              const double dp = double(o.p[q]) - double(P.x[q]);
+              acc[4] += 2.0 * dp * dp;
+            }
           }
+          st_stream(reinterpret_cast<VR*>(B.P + ol), Pn);
+          st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
+          st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
+          st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
+          if (special) {
+            if (dci >= 0) {
+              VR Hn;
 #pragma unroll
-          for (int q = 0; q < VEC; ++q)
-            if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
+              for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
+              *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
+            }
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+              if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
+          }
+        }
+        VR Po, To, Ho;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          Po.x[q] = o.p[q];
+          To.x[q] = o.tm[q];
+          Ho.x[q] = o.half[q];
+        }
+        *reinterpret_cast<VR*>(sP + j * SUB + u * VEC) = Po;
+        *reinterpret_cast<VR*>(sTm + j * SUB + u * VEC) = To;
+        *reinterpret_cast<VR*>(sH + j * SUB + u * VEC) = Ho;
+      }
+      {  // node rows of the next pass, or of the next group's first pass,
+         // in flight during phase 2
+        int64_t o = -1;
+        if (s0 + SUB < Kpp)
+          o = node_vec(tg, ng, s0 + SUB);
+        else if (tg + npp < t1)
+          o = node_vec(tg + npp, min(npp, t1 - tg - npp), 0);
+        if (o >= 0) {
+          pW = *reinterpret_cast<const u32x4*>(A.W + o);
+          pB = *reinterpret_cast<const u32x4*>(A.TB + o);
         }
       }
-      VR Po, To, Ho;
+      lds_barrier();
+      if (own) {
+        const int i = ii, n = n0 + i, p = pp, v = vv;
+        const int k0 = s0 + v * VEC;
+        const R* sdp = sDp + p * kTileDev;
+        const R* sdt = sDt + p * kTileDev;
+        R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        Po.x[q] = o.p[q];
-        To.x[q] = o.tm[q];
-        Ho.x[q] = o.half[q];
+        for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
+        bool first = true;
+        for (int qq = sLp[i]; qq < sLp[i + 1]; ++qq) {
+          const int ent = sTc[qq];
+          const int j = ent >> 1;
+          const bool to_end = ent & 1;
+          const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + uu * VEC);
+          const VR To = *reinterpret_cast<const VR*>(sTm + j * SUB + uu * VEC);
+          const VR Ho = *reinterpret_cast<const VR*>(sH + j * SUB + uu * VEC);
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            const R pj = to_end ? Po.x[q] : -Po.x[q];
+            const R thj = to_end ? To.x[q] - Ho.x[q] : To.x[q] + Ho.x[q];
+            sp[q] += pj;
+            sb[q] += thj;
+            if (first) c[q] = thj;
+            const R d = thj - c[q];
+            s1[q] += d;
+            s2[q] += d * d;
+          }
+          first = false;
+        }
+        for (int qq = sNp[i]; qq < sNp[i + 1]; ++qq) {
+          const R pj = sdp[qq], thj = sdt[qq];
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) {
+            sp[q] += pj;
+            sb[q] += thj;
+            if (first) c[q] = thj;
+            const R d = thj - c[q];
+            s1[q] += d;
+            s2[q] += d * d;
+          }
+          first = false;
+        }
+        const size_t on = (size_t(tg + p) * Kpp + c0) * N + (s0 - c0) + size_t(n) * w + v * VEC;
+        const VR Uo = __builtin_bit_cast(VR, pU);
+        const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + uu * VEC);
+        const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + uu * VEC);
+        const double dg = sDg[i], idg = sIdg[i];
+        const R rdg = R(dg), ridg = R(idg);
+        VR Un, Wn, Bn;
+        R sumw = R(0), sumb = R(0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const bool valid = k0 + q < tp.Kp;
+          const R pb = div_by(sp[q], rdg, ridg);
+          const R tb = div_by(sb[q], rdg, ridg);
+          const R un = Uo.x[q] + pb;
+          const R wn = un + pb;
+          if (check && valid) {
+            const double dpb = double(pb);
+            acc[0] += dg * dpb * dpb;
+            acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) * idg, 0.0);
+            const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
+            acc[2] += dg * dd * dd;
+            const double dt = double(tb) - double(Bo.x[q]);
+            acc[3] += dg * dt * dt;
+          }
+          Un.x[q] = valid ? un : R(0);
+          Wn.x[q] = valid ? wn : R(0);
+          Bn.x[q] = valid ? tb : R(0);
+          sumw += Wn.x[q];
+          sumb += Bn.x[q];
+        }
+        st_stream(reinterpret_cast<VR*>(B.U + on), Un);
+        st_stream(reinterpret_cast<VR*>(B.W + on), Wn);
+        st_stream(reinterpret_cast<VR*>(B.TB + on), Bn);
+        // row sums indexed (node, period, vector): ii * nvt + uu
+        sRw[threadIdx.x] = sumw;
+        sRb[threadIdx.x] = sumb;
       }
-      *reinterpret_cast<VR*>(sP + j * SUB + v * VEC) = Po;
-      *reinterpret_cast<VR*>(sTm + j * SUB + v * VEC) = To;
-      *reinterpret_cast<VR*>(sH + j * SUB + v * VEC) = Ho;
-    }
-    if (s0 + SUB < Kpp) {  // the next pass's node rows, in flight during phase 2
-      const int64_t o = node_vec(s0 + SUB);
-      if (o >= 0) {
-        pW = *reinterpret_cast<const u32x4*>(A.W + o);
-        pB = *reinterpret_cast<const u32x4*>(A.TB + o);
-      }
+      prev_nvc = nvc;
     }
     lds_barrier();
-    if (own) {
-      const int x = threadIdx.x, i = ii, v = vv, n = n0 + i;
-      const int k0 = s0 + v * VEC;
-      R sp[VEC], sb[VEC], c[VEC], s1[VEC], s2[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) sp[q] = sb[q] = c[q] = s1[q] = s2[q] = R(0);
-      bool first = true;
-      for (int qq = sLp[i]; qq < sLp[i + 1]; ++qq) {
-        const int ent = sTc[qq];
-        const int j = ent >> 1;
-        const bool to_end = ent & 1;
-        const VR Po = *reinterpret_cast<const VR*>(sP + j * SUB + v * VEC);
-        const VR To = *reinterpret_cast<const VR*>(sTm + j * SUB + v * VEC);
-        const VR Ho = *reinterpret_cast<const VR*>(sH + j * SUB + v * VEC);
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          const R pj = to_end ? Po.x[q] : -Po.x[q];
-          const R thj = to_end ? To.x[q] - Ho.x[q] : To.x[q] + Ho.x[q];
-          sp[q] += pj;
-          sb[q] += thj;
-          if (first) c[q] = thj;
-          const R d = thj - c[q];
-          s1[q] += d;
-          s2[q] += d * d;
-        }
-        first = false;
+    if (int(threadIdx.x) < cn * ng) {
+      const int i = int(threadIdx.x) / ng, p = int(threadIdx.x) - i * ng;
+      // (sAcc holds the earlier passes of a period taken in several passes,
+      // and zero otherwise)
+      double aw = ng == 1 ? sAccW[i] : 0.0, ab = ng == 1 ? sAccB[i] : 0.0;
+      for (int v = 0; v < prev_nvc; ++v) {
+        aw += double(sRw[(i * ng + p) * prev_nvc + v]);
+        ab += double(sRb[(i * ng + p) * prev_nvc + v]);
       }
-      for (int qq = sNp[i]; qq < sNp[i + 1]; ++qq) {
-        const R pj = sDp[qq], thj = sDt[qq];
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          sp[q] += pj;
-          sb[q] += thj;
-          if (first) c[q] = thj;
-          const R d = thj - c[q];
-          s1[q] += d;
-          s2[q] += d * d;
-        }
-        first = false;
-      }
-      const size_t on = nbase + size_t(n) * w + v * VEC;
-      const VR Uo = __builtin_bit_cast(VR, pU);
-      const VR Wo = *reinterpret_cast<const VR*>(sW + i * SUB + v * VEC);
-      const VR Bo = *reinterpret_cast<const VR*>(sB + i * SUB + v * VEC);
-      const double dg = sDg[i], idg = sIdg[i];
-      const R rdg = R(dg), ridg = R(idg);
-      VR Un, Wn, Bn;
-      R sumw = R(0), sumb = R(0);
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        const bool valid = k0 + q < tp.Kp;
-        const R pb = div_by(sp[q], rdg, ridg);
-        const R tb = div_by(sb[q], rdg, ridg);
-        const R un = Uo.x[q] + pb;
-        const R wn = un + pb;
-        if (check && valid) {
-          const double dpb = double(pb);
-          acc[0] += dg * dpb * dpb;
-          acc[1] += fmax(double(s2[q]) - double(s1[q]) * double(s1[q]) * idg, 0.0);
-          const double dd = dpb - double(Wo.x[q] - Uo.x[q]);
-          acc[2] += dg * dd * dd;
-          const double dt = double(tb) - double(Bo.x[q]);
-          acc[3] += dg * dt * dt;
-        }
-        Un.x[q] = valid ? un : R(0);
-        Wn.x[q] = valid ? wn : R(0);
-        Bn.x[q] = valid ? tb : R(0);
-        sumw += Wn.x[q];
-        sumb += Bn.x[q];
-      }
-      st_stream(reinterpret_cast<VR*>(B.U + on), Un);
-      st_stream(reinterpret_cast<VR*>(B.W + on), Wn);
-      st_stream(reinterpret_cast<VR*>(B.TB + on), Bn);
-      sRw[x] = sumw;
-      sRb[x] = sumb;
+      const size_t o = size_t(n0 + i) * T + tg + p;
+      a.st.avgW[o] = R(aw / double(tp.Kp));
+      a.st.avgTB[o] = R(ab / double(tp.Kp));
     }
-    prev_nvc = nvc;
-  }
-  lds_barrier();
-  if (threadIdx.x < cn) {
-    for (int v = 0; v < prev_nvc; ++v) {
-      runW += double(sRw[threadIdx.x * prev_nvc + v]);
-      runB += double(sRb[threadIdx.x * prev_nvc + v]);
-    }
-    const size_t o = size_t(n0 + threadIdx.x) * T + t;
-    a.st.avgW[o] = R(runW / double(tp.Kp));
-    a.st.avgTB[o] = R(runB / double(tp.Kp));
   }
 }
 
@@ -648,11 +695,15 @@ k_sweep_tile(KArgs<R, VT> a) {
   const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
   const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
   __shared__ double sh[kTileBlock / kWave];
-  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, int64_t(tp.T) * tp.Q);
+  // work items: (run of tile_run periods, cluster), clusters innermost
+  const int run = a.g.tile_run;
+  const int64_t n_items = int64_t((tp.T + run - 1) / run) * tp.Q;
+  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, n_items);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t item = sweep.first; item < sweep.end; item += sweep.step) {
-    const int t = int(item / tp.Q), cq = int(item - int64_t(t) * tp.Q);
-    tile_item<R, VT, GEN>(a, A, B, t, cq, rp, rt, sv, check, acc);
+    const int r = int(item / tp.Q), cq = int(item - int64_t(r) * tp.Q);
+    const int t0 = r * run;
+    tile_run<R, VT, GEN>(a, A, B, cq, t0, min(tp.T, t0 + run), rp, rt, sv, check, acc);
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -924,7 +975,12 @@ __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu
 k_sweep_tile_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
   __shared__ double sh[kTileBlock / kWave];
-  const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_tiles);
+  // XCD ranges of the work list split by estimated work, not by count
+  const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+  Sweep sweep;
+  sweep.first = tab.xcd_bounds[x] + (blockIdx.x >> 3);
+  sweep.end = tab.xcd_bounds[x + 1];
+  sweep.step = per;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int cur_i = -1;
   auto flush = [&](int i) {
@@ -956,8 +1012,10 @@ k_sweep_tile_batch(BatchTab tab) {
     const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
     const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
     const int64_t li = g - tab.tile_prefix[i];
-    const int t = int(li / a.tp.Q), cq = int(li - int64_t(t) * a.tp.Q);
-    tile_item<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], t, cq, rp, rt, sv, check, acc);
+    const int r = int(li / a.tp.Q), cq = int(li - int64_t(r) * a.tp.Q);
+    const int t0 = r * a.g.tile_run;
+    tile_run<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], cq, t0,
+                         min(a.tp.T, t0 + a.g.tile_run), rp, rt, sv, check, acc);
   }
   if (cur_i >= 0) flush(cur_i);
   zero_between(cur_i, tab.n_inst);

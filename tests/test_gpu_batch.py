@@ -185,7 +185,7 @@ def _tuning_cache(path, insts, precision, grid_factor):
     sKT = sum((x.K + 1) * x.T for x in insts)
     key = f"{arch}|p{precision}|n{len(insts)}|NT{sN}|LT{sL}|KT{sKT}"
     with open(path, "w") as fh:
-        fh.write(f"{key} 0 {grid_factor} -1 1.0\n")
+        fh.write(f"{key} 0 {grid_factor} -1 1 1.0\n")
 
 
 def test_batch_residuals_survive_a_smaller_grid():
