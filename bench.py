@@ -38,10 +38,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash, dtype):
-    """HBM bytes per launch of the sweep kernel from committed counter runs,
-    if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"sweep_kernel_large_{dtype}_traffic.json")
+def traffic_from_profiles(kernel_hash, workload, dtype):
+    """HBM bytes per launch of a sweep kernel from committed counter runs
+    (profiles/sweep_kernel_<workload>_<dtype>_traffic.json), if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_kernel_{workload}_{dtype}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -67,9 +68,21 @@ def time_iterations(solver, steps, warmup):
     return t1 - t0, kt
 
 
+TUNING_CACHE = None
+
+
+def _autotune(solver):
+    """The library's autotuner (tiled vs node rows, period groups, grid) on
+    this solver's instances, through the tuning cache when one is given, so
+    that profiler runs time the configuration the plain run chose."""
+    t = solver.autotune(trials=10, cache_path=TUNING_CACHE)
+    return {k: t[k] for k in ("tiled", "tile_groups", "lanes_shift", "grid_factor")}
+
+
 def batched_rates(iters, dtype, dual_dtype):
     """Aggregate instance-iterations/s of the 64 uneven instances as one batch
-    and solved one at a time, both in 50-iteration graph blocks."""
+    and solved one at a time, both in 50-iteration graph blocks, each
+    configuration picked by the autotuner first."""
     import torch
     from paper_2410_17203_amd import synth
     from paper_2410_17203_amd.binding import Solver
@@ -78,6 +91,7 @@ def batched_rates(iters, dtype, dual_dtype):
 
     def run(arg):
         s = Solver(arg, **opts)
+        _autotune(s)
         s.solve()  # warm-up: builds the graphs
         s.reset()
         torch.cuda.synchronize()
@@ -92,11 +106,38 @@ def batched_rates(iters, dtype, dual_dtype):
     t_single = sum(run(i) for i in insts)
     n = len(insts)
     elems = sum((13 * i.L + 2 * (i.G + i.D + i.B) + 6 * i.N) * (i.K + 1) * i.T for i in insts)
-    return {"instances": n, "iters": iters, "state_dtype": dtype, "dual_dtype": dual_dtype,
-            "batched_inst_iters_per_s": n * iters / t_batch,
-            "one_at_a_time_inst_iters_per_s": n * iters / t_single,
-            "speedup": t_single / t_batch,
-            "algorithmic_elements_per_iteration": elems}
+    out = {"instances": n, "iters": iters, "state_dtype": dtype, "dual_dtype": dual_dtype,
+           "batched_inst_iters_per_s": n * iters / t_batch,
+           "one_at_a_time_inst_iters_per_s": n * iters / t_single,
+           "speedup": t_single / t_batch,
+           "algorithmic_elements_per_iteration": elems}
+    # per-kernel times of the batch (events around each launch, so no graphs)
+    s = Solver(insts, dtype=dtype, dual_dtype=dual_dtype, polish_fp64=0, eps=0.0,
+               min_iter=2**31 - 1, max_iter=2**31 - 1)
+    out["tuning"] = _autotune(s)
+    s.iterate(5)
+    s.synchronize()
+    s.set_timing(True)
+    s.iterate(iters)
+    s.synchronize()
+    kt = s.kernel_times()
+    s.close()
+    sweep_ms = kt["sweep"]["ms"] / max(kt["sweep"]["launches"], 1)
+    out["kernel_ms_per_launch"] = {k: v["ms"] / max(v["launches"], 1) for k, v in kt.items()}
+    if dtype == dual_dtype:
+        # contracted bytes of the sweep, as for the single-instance line
+        S = 4 if dtype == "f32" else 8
+        sweep_bytes = S * sum((13 * i.L + 6 * i.N) * (i.K + 1) * i.T for i in insts)
+        traffic = traffic_from_profiles(kernel_source_hash(), "batch64", dtype)
+        out["sweep_roofline"] = {
+            "bound": "hbm", "kernel": "k_sweep_tile_batch", "ms_per_launch": sweep_ms,
+            "algorithmic_bytes_per_launch": sweep_bytes,
+            "achieved": sweep_bytes / (sweep_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": sweep_bytes / (sweep_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "frac_counters": (None if traffic is None
+                              else traffic / (sweep_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)}
+    return out
 
 
 def batched_time_to_tolerance(max_iter):
@@ -111,6 +152,7 @@ def batched_time_to_tolerance(max_iter):
     from paper_2410_17203_amd.binding import Solver
     insts = synth.batched()
     b = Solver(insts, dtype="f32", eps=1e-3, max_iter=max_iter)
+    _autotune(b)
     b.solve()  # warm-up: builds the graphs
     b.reset()
     torch.cuda.synchronize()
@@ -125,6 +167,7 @@ def batched_time_to_tolerance(max_iter):
     t_single, conv_s, iters_s = 0.0, [], []
     for inst in insts:
         s = Solver(inst, dtype="f32", eps=1e-3, max_iter=max_iter, polish_fp64=0)
+        _autotune(s)
         s.solve()
         s.reset()
         torch.cuda.synchronize()
@@ -306,32 +349,40 @@ def summarize_stats(directory, out_path, command):
     print("\n".join(lines))
 
 
-def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_write,
-                      request_dir=None, command_request=None):
-    """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
-    dispatch), each scaled by what the counter reads for a plain 1 GiB -> 1 GiB
-    elementwise copy in the same run."""
+def summarize_traffic(fetch_dir, write_dir, out_path, kernel, workload, command_fetch,
+                      command_write, request_dir=None, command_request=None):
+    """HBM bytes per launch of the kernels whose names contain one of the
+    '|'-separated `kernel` patterns, from FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by what the counter reads for a plain
+    1 GiB -> 1 GiB elementwise copy in the same run."""
+    patterns = [k for k in kernel.split("|") if k]
+
+    def hit(name):
+        return any(k in name for k in patterns)
+
     def per_kernel(directory, counter):
         rows = [r for r in _read_csv(_find(directory, "counter_collection.csv",
                                            "counter_collection_trace.csv"))
                 if r["Counter_Name"] == counter]
         copy = [float(r["Counter_Value"]) for r in rows if "MulFunctor" in r["Kernel_Name"]]
-        sweep = [float(r["Counter_Value"]) for r in rows
-                 if "k_sweep<" in r["Kernel_Name"] or "k_sweep_tile<" in r["Kernel_Name"]]
+        sweep = [float(r["Counter_Value"]) for r in rows if hit(r["Kernel_Name"])]
         if not copy or not sweep:
-            raise RuntimeError(f"{counter}: copy or sweep dispatches missing")
+            raise RuntimeError(f"{counter}: copy or {kernel} dispatches missing")
         copy_kib = sum(copy) / len(copy)
         factor = 2.0**20 / copy_kib  # the copy moves exactly 1 GiB each way
+        spread[counter] = [min(sweep), max(sweep)]
         return factor, copy_kib, sum(sweep) / len(sweep), len(sweep)
+    spread = {}
     fr, fcopy, fsweep, nf = per_kernel(fetch_dir, "FETCH_SIZE")
     wr, wcopy, wsweep, nw = per_kernel(write_dir, "WRITE_SIZE")
     read_b = fsweep * 1024 * fr
     write_b = wsweep * 1024 * wr
-    d = {"kernel": "k_sweep_tile", "workload": "large (N=10000 L=13000 T=96 K=200), FP32 iterate",
+    d = {"kernel": kernel, "workload": workload,
          "kernel_source_hash": kernel_source_hash(),
          "fetch_kib_per_launch_raw": fsweep, "write_kib_per_launch_raw": wsweep,
          "copy_fetch_kib_raw": fcopy, "copy_write_kib_raw": wcopy,
          "fetch_scale": fr, "write_scale": wr, "launches": [nf, nw],
+         "min_max_kib_raw": spread,
          "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
          "hbm_bytes_per_launch": read_b + write_b,
          "command_fetch": command_fetch, "command_write": command_write}
@@ -341,7 +392,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command_fetch, command_wri
         rows = _read_csv(_find(request_dir, "counter_collection.csv", "counter_collection_trace.csv"))
         per = {}
         for r in rows:
-            if "k_sweep<" in r["Kernel_Name"] or "k_sweep_tile<" in r["Kernel_Name"]:
+            if hit(r["Kernel_Name"]):
                 per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         avg = {k: sum(v) / len(v) for k, v in per.items()}
         d["read_requests_per_launch"] = {k.replace("TCC_EA0_", ""): v for k, v in avg.items()}
@@ -379,6 +430,9 @@ def main():
     ap.add_argument("--cpu-sample-k", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--cpu-medium-iters", type=int, default=40)
+    ap.add_argument("--tuning-cache", default=None,
+                    help="autotuner cache file for the batched legs (read, and appended "
+                         "to when a configuration is new)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="1: first run a plain 1 GiB -> 1 GiB copy kernel three times "
                          "(reference for the HBM byte counters)")
@@ -386,9 +440,10 @@ def main():
                     help="host only: summarise a rocprofv3 --stats run and exit")
     ap.add_argument("--summarize-traffic", nargs="+",
                     metavar="ARG",
-                    help="host only: FETCH_DIR WRITE_DIR OUT CMD_FETCH CMD_WRITE "
-                         "[REQUEST_DIR CMD_REQUEST]: HBM bytes per sweep launch from the "
-                         "--pmc runs, then exit")
+                    help="host only: FETCH_DIR WRITE_DIR OUT KERNEL WORKLOAD CMD_FETCH "
+                         "CMD_WRITE [REQUEST_DIR CMD_REQUEST]: HBM bytes per launch of the "
+                         "kernels matching KERNEL ('|'-separated name fragments) from "
+                         "the --pmc runs, then exit")
     args = ap.parse_args()
 
     if args.summarize_stats:
@@ -407,6 +462,8 @@ def main():
     from paper_2410_17203_amd import synth
     from paper_2410_17203_amd.binding import Solver
 
+    global TUNING_CACHE
+    TUNING_CACHE = args.tuning_cache
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.calibrate_copy:
         x = torch.ones(2**28, dtype=torch.float32, device="cuda")
@@ -552,7 +609,7 @@ def main():
                 f"(recorded {a['forward_recorded_s']:.3f}s), backward {a['backward_s']:.3f}s")
 
     khash = kernel_source_hash()
-    traffic = traffic_from_profiles(khash, args.dtype)
+    traffic = traffic_from_profiles(khash, args.config, args.dtype)
     out = {
         "metric": METRIC,
         "value": value,

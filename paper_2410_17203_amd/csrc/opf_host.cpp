@@ -1946,8 +1946,21 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
       }
   }
   if (!cached) {
-    const bool timing = c->timing;
+    // trials run untimed full iterations whatever the stopping options: no
+    // instance may stop (converged or at max_iter) and turn later trials into
+    // no-ops; options and the timing switch come back on every exit
+    struct Restore {
+      opf_ctx* c;
+      opf_options opt;
+      bool timing;
+      ~Restore() {
+        c->opt = opt;
+        c->timing = timing;
+      }
+    } restore{c, c->opt, c->timing};
     c->timing = false;
+    c->opt.max_iter = INT32_MAX;
+    c->opt.min_iter = INT32_MAX;
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -1996,7 +2009,6 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->timing = timing;
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);
       outf << key.str() << " " << best.lanes_shift << " " << best.grid_factor << " "

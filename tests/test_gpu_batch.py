@@ -146,6 +146,26 @@ def test_autotune_resets_and_caches():
     b.close()
 
 
+def test_autotune_times_full_iterations_whatever_the_stopping_options():
+    """Trial iterations ignore max_iter and the tolerance (an instance that
+    stopped would make later trials no-ops and win them), and the options
+    are back in force afterwards."""
+    from paper_2410_17203_amd.binding import Solver
+    say("[batch] autotune under tight stopping options")
+    insts = batch_instances()
+    free = Solver(insts, dtype="f32", eps=0.0, max_iter=10**6)
+    t_free = free.autotune(trials=8)
+    free.close()
+    tight = Solver(insts, dtype="f32", eps=1e-1, max_iter=2)
+    t_tight = tight.autotune(trials=8)
+    say(f"  ms/iteration: {t_free['ms_per_iter']:.4f} free, {t_tight['ms_per_iter']:.4f} tight")
+    assert t_tight["ms_per_iter"] > 0.5 * t_free["ms_per_iter"]
+    tight.solve()
+    # max_iter is back in force after the trials
+    assert max(tight.residuals(i)["iter"] for i in range(len(insts))) == 2
+    tight.close()
+
+
 def test_batched_bf16_duals_run():
     from paper_2410_17203_amd.binding import Solver
     say("[batch] bf16 duals")
