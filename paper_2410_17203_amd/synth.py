@@ -25,12 +25,36 @@ Generation recipe (every random draw has its own named PCG64 sub-stream):
 * batteries on distinct nodes: energy E U[1, 4], power P = E/4,
   duration 4, efficiency 0.95, discharge cost 1;
 * contingencies: K distinct non-bridge lines (so every post-outage grid
-  stays connected and flows are unique);
+  stays connected and flows are unique) that a generator redispatch can
+  idle in every period (below);
 * feasibility: pmax is scaled so that total capacity is at least 1.25x the
-  peak total load, then every line capacity is raised to 1.1x the largest
-  base or post-outage flow of a reference dispatch (generators proportional
-  to pmax, batteries idle) computed with DC power flow.  That reference
-  dispatch is then N-1 feasible, so the convex problem has a solution.
+  peak total load.  The reference dispatch starts with generators
+  proportional to pmax (batteries idle).  Non-bridge lines are then tried
+  in a seeded random order, and a line becomes an outage if the dispatch,
+  corrected to carry no power on it and on every outage already taken
+  (least change in the metric weighted by pmax, so that the balance and
+  the earlier outages stay exact), keeps every generator within
+  [0.01 pmax, 1.5 pmax] and within 0.99 of its ramp limit; pmax is raised
+  to 1/0.99 of a dispatch above it and the ramp limit is 0.3 pmax.  Every
+  line capacity is then raised to 1.1x the largest base or post-outage
+  flow of that dispatch (DC power flow).
+  Why: in the problem of Section 2.3 the power and the phase of every
+  device node are shared by all contingencies.  Where most nodes host a
+  device (as in these grids and the paper's), the flows of the lines
+  between them are then the same in every contingency, so a feasible point
+  needs (nearly) zero base flow on each outaged line; a capacity rule for
+  free post-outage phases (the textbook N-1 problem) does not provide one,
+  and grids with uniformly drawn outages are in general infeasible.  The
+  reference dispatch above carries no power on the outaged lines, so its
+  base phases, used unchanged in every contingency, satisfy every
+  contingency's balance and every capacity: the instance is feasible for
+  the problem as posed (and for the textbook N-1 problem).
+  Where fewer than K lines pass (small grids: K outages and the balance
+  need at least K + 1 generators), the remaining outages are drawn
+  uniformly from the other candidates and the instance is certified for
+  free post-outage phases only (`meta["K_idle"]` < K); `outage_rule=
+  "idle_only"` keeps only the idle lines instead (fewer contingencies), and
+  `outage_rule="uniform"` draws all K uniformly.
 """
 from __future__ import annotations
 
@@ -263,9 +287,10 @@ def _raise_caps_for_n1(N, frm, to, sus, cap, outage, inj):
     """Raise capacities to 1.1x the worst base/post-outage reference flow."""
     flows, lu = _dc_flows(N, frm, to, sus, inj)
     worst = np.abs(flows).max(axis=1)
+    scale = max(1.0, float(np.abs(flows).max())) if flows.size else 1.0
     for o in outage:
-        if o < 0:
-            continue
+        if o < 0 or np.abs(flows[o]).max() <= 1e-9 * scale:
+            continue  # an idle line's outage leaves every flow as it is
         rhs = np.zeros(N)
         rhs[frm[o]] += 1.0
         rhs[to[o]] -= 1.0
@@ -282,9 +307,74 @@ def _raise_caps_for_n1(N, frm, to, sus, cap, outage, inj):
     return new_cap, float(np.mean(new_cap > cap))
 
 
+def _idle_outages(N, frm, to, sus, gen_node, load_node, demand, pmax1, disp, order, K,
+                  use_ramp):
+    """Greedy choice of up to K outages from `order` that a generator
+    redispatch idles in every period (recipe in the module docstring).
+
+    Returns (outages, dispatch [G, T], pmax [G]).  The correction for each
+    new line is the pmax-weighted least-norm change that zeroes its flow
+    while keeping the balance and the earlier zero flows: with A the
+    accepted constraint rows over generator injections (first row: the
+    balance) and W = diag(pmax), the direction is g = W a - W A^T M^-1 A W a
+    with M = A W A^T, which A maps to zero."""
+    G, T = gen_node.shape[0], demand.shape[1]
+    _, lu = _dc_flows(N, frm, to, sus, np.zeros((N, 1)))
+    W = np.asarray(pmax1, dtype=np.float64)
+    A = np.ones((1, G))
+    Minv = np.array([[1.0 / W.sum()]])
+    p = disp.copy()
+    pmax = W.copy()
+    taken = []
+    xs = {}
+    for i, l in enumerate(order):
+        if len(taken) == K:
+            break
+        if l not in xs:  # sensitivities of the next candidates, one solve per block
+            blk = order[i:i + 64]
+            rhs = np.zeros((N, len(blk)))
+            rhs[frm[blk], np.arange(len(blk))] += 1.0
+            rhs[to[blk], np.arange(len(blk))] -= 1.0
+            x = np.zeros((N, len(blk)))
+            if N > 1:
+                x[1:] = lu.solve(np.ascontiguousarray(rhs[1:]))
+            xs = {int(c): x[:, j] for j, c in enumerate(blk)}
+        s_n = sus[l] * xs[int(l)]  # flow on l per unit injected at each node (out at node 0)
+        a = s_n[gen_node]
+        flow = a @ p - s_n[load_node] @ demand  # [T]
+        Wa = W * a
+        m = A @ Wa
+        Mm = Minv @ m
+        g = Wa - W * (A.T @ Mm)
+        sc = float(a @ g)
+        if not sc > 1e-9 * float(a @ Wa):
+            continue  # the earlier rows already fix this flow
+        q = p - g[:, None] * (flow[None, :] / sc)
+        if not (np.all(q >= 0.01 * pmax[:, None]) and np.all(q <= 1.5 * pmax[:, None])):
+            continue
+        if use_ramp and T > 1:
+            pm = np.maximum(pmax, q.max(axis=1) / 0.99)
+            if not np.all(np.abs(np.diff(q, axis=1)) <= 0.99 * 0.3 * pm[:, None]):
+                continue
+        p = q
+        taken.append(int(l))
+        # bordered inverse of M with the new row a appended to A
+        Minv = np.block([[Minv + np.outer(Mm, Mm) / sc, -Mm[:, None] / sc],
+                         [-Mm[None, :] / sc, np.array([[1.0 / sc]])]])
+        A = np.vstack([A, a])
+    pmax = np.maximum(pmax, p.max(axis=1) / 0.99) if T > 0 else pmax
+    return np.sort(np.asarray(taken, dtype=np.int32)), p, pmax
+
+
 def make_instance(name: str, N: int, L: int, G: int, D: int, B: int, T: int, K: int,
-                  seed: int, ramp: Optional[bool] = None) -> Instance:
-    """Build one seeded synthetic instance (recipe in the module docstring)."""
+                  seed: int, ramp: Optional[bool] = None, outage_rule: str = "idle") -> Instance:
+    """Build one seeded synthetic instance (recipe in the module docstring).
+
+    outage_rule: "idle" (outages that a redispatch idles, topped up with
+    uniform draws if too few exist), "idle_only" (only those: K may shrink,
+    `meta["K_requested"]` keeps the request) or "uniform"."""
+    if outage_rule not in ("idle", "idle_only", "uniform"):
+        raise ValueError(f"unknown outage_rule {outage_rule!r}")
     ss = np.random.SeedSequence(seed)
     topo, lines, gens, loads, bats, cont = [np.random.Generator(np.random.PCG64(s))
                                             for s in ss.spawn(6)]
@@ -314,23 +404,37 @@ def make_instance(name: str, N: int, L: int, G: int, D: int, B: int, T: int, K: 
     bat_eta = np.full(B, 0.95)
     bat_alpha = np.full(B, 1.0)
 
-    # contingencies: K distinct non-bridge lines
+    # contingency candidates: distinct non-bridge lines
     br = bridges(N, frm, to)
     cand = np.nonzero(~br)[0]
     if K > len(cand):
         raise ValueError(f"only {len(cand)} non-bridge lines for K={K}")
-    outage = np.sort(cont.choice(cand, size=K, replace=False)).astype(np.int32)
 
     # feasibility rule
     peak = demand.sum(axis=0).max() if D > 0 else 0.0
     scale = max(1.0, 1.25 * peak / max(pmax1.sum(), 1e-12))
     pmax1 = pmax1 * scale
-    pmax = np.repeat(pmax1[:, None], T, axis=1)
-    pmin = np.zeros((G, T))
     use_ramp = (T > 1) if ramp is None else ramp
-    gen_ramp = 0.3 * pmax1 if use_ramp else np.zeros(G)
     total = demand.sum(axis=0)  # [T]
     disp = pmax1[:, None] * (total / pmax1.sum())[None, :]
+    K_req = K
+    if outage_rule != "uniform" and K > 0:
+        order = cont.permutation(cand)
+        outage, disp, pmax1 = _idle_outages(N, frm, to, sus, gen_node, load_node, demand,
+                                            pmax1, disp, order, K, use_ramp)
+        K_idle = int(outage.shape[0])
+        if outage_rule == "idle_only":
+            K = K_idle
+        elif K_idle < K:
+            rest = np.setdiff1d(cand, outage)
+            more = cont.choice(rest, size=K - K_idle, replace=False)
+            outage = np.sort(np.r_[outage, more]).astype(np.int32)
+    else:
+        outage = np.sort(cont.choice(cand, size=K, replace=False)).astype(np.int32)
+        K_idle = 0
+    pmax = np.repeat(pmax1[:, None], T, axis=1)
+    pmin = np.zeros((G, T))
+    gen_ramp = 0.3 * pmax1 if use_ramp else np.zeros(G)
     inj = np.zeros((N, T))
     np.add.at(inj, gen_node, disp)
     np.subtract.at(inj, load_node, demand)
@@ -346,8 +450,11 @@ def make_instance(name: str, N: int, L: int, G: int, D: int, B: int, T: int, K: 
         bat_node=bat_node, bat_P=bat_P, bat_dur=bat_dur, bat_eta=bat_eta,
         bat_alpha=bat_alpha,
         meta={"seed": seed, "frac_lines_raised": frac, "capacity_scale": scale,
+              "K_requested": K_req, "K_idle": K_idle, "outage_rule": outage_rule,
               # the reference dispatch [G, T] (batteries idle) that certifies
-              # feasibility with free post-outage phases
+              # feasibility: N-1 with free post-outage phases always, and with
+              # the device phases shared by all contingencies when every
+              # outage is idle (K_idle == K: no power on any outaged line)
               "ref_dispatch": disp},
     )
 
@@ -386,7 +493,11 @@ def batched_configs(n: int = 64, seed: int = 64) -> List[dict]:
 
 
 def batched(n: int = 64, seed: int = 64) -> List[Instance]:
-    return [make_instance(f"batch{i}", **kw) for i, kw in enumerate(batched_configs(n, seed))]
+    """The batch of uneven instances; each keeps only outages that a
+    redispatch idles, so every instance is feasible with shared device
+    phases (a few get fewer contingencies than drawn)."""
+    return [make_instance(f"batch{i}", outage_rule="idle_only", **kw)
+            for i, kw in enumerate(batched_configs(n, seed))]
 
 
 def two_node(d: float = 1.0, c2=(0.5, 0.25), c1=(1.0, 2.0), pmax=(5.0, 5.0),

@@ -246,3 +246,28 @@ def test_fp32_adjoint_on_diff_workload_close_to_fp64():
 
 
 FP32_DIFF_BAR = 5e-3
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-5), ("f32", 2e-3)])
+def test_unrolled_adjoint_reaches_the_envelope_sensitivities(dtype, bar):
+    """Section 5.5 on the Tiny grid: the library's adjoint of the cost after
+    1500 unrolled iterations from zero equals the exact derivatives of the
+    optimal cost (the node prices for the loads, minus the limit duals for
+    the generator limits), computed from the exact QP independently of the
+    message-passing arithmetic (tests/adj_cases.py), within `bar` relative
+    to the largest derivative; after 100 iterations it does not yet."""
+    from tests.adj_cases import tiny_exact_sensitivities
+
+    say(f"[adjoint] envelope sensitivities, tiny, {dtype}")
+    inst, g_load, g_pmax, _ = tiny_exact_sensitivities()
+    J = len(inst.gen_node) + len(inst.load_node) + len(inst.bat_node)
+    w = np.zeros((J, int(inst.T)))
+    errs = []
+    for n in (100, 1500):
+        g, _, _ = gpu_grads(inst, n, w, 1.0, dtype=dtype, every=50)
+        e_load = float((g["load"][:, 0].numpy() - g_load).__abs__().max()) / np.abs(g_load).max()
+        e_pmax = float((g["pmax"][:, 0].numpy() - g_pmax).__abs__().max()) / np.abs(g_pmax).max()
+        say(f"  {n} iterations: load {e_load:.2e}, pmax {e_pmax:.2e}")
+        errs.append(max(e_load, e_pmax))
+    assert errs[0] > bar
+    assert errs[1] <= bar, errs

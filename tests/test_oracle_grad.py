@@ -53,3 +53,37 @@ def test_autograd_matches_central_differences(adapt):
             dn[which][idx] -= H
             fd = (f(up) - f(dn)) / (2 * H)
             assert abs(float(g[idx]) - fd) <= 1e-6 * max(1.0, abs(fd)), (which, idx, float(g[idx]), fd)
+
+
+def test_converged_prices_and_unrolled_derivatives_reach_the_envelope_sensitivities():
+    """Section 5.5: at the optimum the derivative of the total cost with
+    respect to a generator's limit is minus the limit's dual, and with
+    respect to a load's demand the node's price (envelope theorem).  Both
+    are computed from the exact QP (tests/adj_cases.py), independently of
+    the oracle.  The converged oracle's prices -rho_p sum_k u_k equal the
+    load derivatives, and its unrolled autograd derivative approaches both
+    sets as the number of iterations grows (the paper's observation), to
+    within 1e-5 after 1500 iterations from zero."""
+    from tests.adj_cases import tiny_exact_sensitivities
+
+    inst, g_load, g_pmax, cost = tiny_exact_sensitivities()
+    assert np.abs(g_pmax).max() > 1.0  # a generator sits at its limit
+    s = Oracle(inst, Options(eps=1e-9, max_iter=200000))
+    r = s.solve()
+    assert r.converged
+    assert abs(r.objective - cost) <= 1e-6 * abs(cost)
+    lmp = s.lmp()[:, 0].numpy()
+    np.testing.assert_allclose(lmp[inst.load_node], g_load, rtol=1e-6)
+
+    errs = []
+    for n in (100, 1500):
+        ld = torch.tensor(np.asarray(inst.load_d, float), requires_grad=True)
+        pm = torch.tensor(np.asarray(inst.gen_pmax, float), requires_grad=True)
+        o = Oracle(inst, Options(eps=1e-12), load_d=ld, gen_pmax=pm)
+        o.run(n)
+        o.objective().backward()
+        e_load = np.abs(ld.grad[:, 0].numpy() - g_load).max() / np.abs(g_load).max()
+        e_pmax = np.abs(pm.grad[:, 0].numpy() - g_pmax).max() / np.abs(g_pmax).max()
+        errs.append(max(e_load, e_pmax))
+    assert errs[1] < errs[0]
+    assert errs[1] <= 1e-5, errs
