@@ -216,6 +216,8 @@ def adjoint_times(n_iters, every, dtype):
     J = len(inst.gen_node) + len(inst.load_node) + len(inst.bat_node)
     w = np.random.default_rng(2024).normal(size=(J, inst.T))
     s = Solver(inst, dtype=dtype, polish_fp64=0)
+    if every is None:
+        every = s.checkpoint_interval(n_iters)
     s.tape_forward(50, every)  # warm-up
     s.adjoint(w, 1.0)
     torch.cuda.synchronize()
@@ -224,6 +226,7 @@ def adjoint_times(n_iters, every, dtype):
     t1 = time.perf_counter()
     s.adjoint(w, 1.0)
     t2 = time.perf_counter()
+    tape_gib = s.tape.numel() / 2**30
     plain = Solver(inst, dtype=dtype, polish_fp64=0, eps=0.0, min_iter=2**31 - 1,
                    max_iter=2**31 - 1)
     plain.iterate(20)
@@ -235,7 +238,7 @@ def adjoint_times(n_iters, every, dtype):
     s.close()
     plain.close()
     return {"workload": "diff: N=500 L=700 G=100 D=400 B=20 T=24 K=20 (synthetic, seed 2024)",
-            "dtype": dtype, "iters": n_iters, "checkpoint_every": every,
+            "dtype": dtype, "iters": n_iters, "checkpoint_every": every, "tape_GiB": tape_gib,
             "forward_plain_s": t4 - t3, "forward_recorded_s": t1 - t0, "backward_s": t2 - t1,
             "backward_over_forward": (t2 - t1) / (t4 - t3)}
 
@@ -603,9 +606,12 @@ def main():
         log(f"[bench] general line model: {g['iters_per_s']:.2f} it/s, sweep {g['sweep_ms']:.3f} ms")
 
     if args.adjoint:
-        extra["adjoint"] = [adjoint_times(1000, 50, "f32"), adjoint_times(1000, 50, "f64")]
+        # checkpoint interval chosen by the memory rule (every iterate kept
+        # when the tape fits in a quarter of free HBM), and every 50th kept
+        extra["adjoint"] = [adjoint_times(1000, None, "f32"), adjoint_times(1000, None, "f64"),
+                            adjoint_times(1000, 50, "f32")]
         for a in extra["adjoint"]:
-            log(f"[bench] adjoint {a['dtype']}: forward {a['forward_plain_s']:.3f}s "
+            log(f"[bench] adjoint {a['dtype']} (checkpoints every {a['checkpoint_every']}): forward {a['forward_plain_s']:.3f}s "
                 f"(recorded {a['forward_recorded_s']:.3f}s), backward {a['backward_s']:.3f}s")
 
     khash = kernel_source_hash()

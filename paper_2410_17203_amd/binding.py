@@ -386,10 +386,28 @@ class Solver:
                                            c_size_t(blob.numel())))
 
     # -- derivatives through unrolled iterations ------------------------------
-    def tape_forward(self, n_iters: int, checkpoint_every: int = 50) -> Dict:
+    def checkpoint_interval(self, n_iters: int, budget_frac: float = 0.25) -> int:
+        """The smallest checkpoint interval among 1, 2, 5, 10, 25, 50 whose
+        tape for n_iters iterations fits in budget_frac of the device's free
+        memory (50 if none does).  Interval 1 keeps every iterate, so the
+        adjoint recomputes nothing."""
+        free, _ = self.torch.cuda.mem_get_info(self.device)
+        nbytes = c_size_t()
+        for every in (1, 2, 5, 10, 25, 50):
+            self._check(self.lib.opf_tape_workspace_size(self.ctx, int(n_iters), every,
+                                                         byref(nbytes)))
+            if nbytes.value <= budget_frac * free:
+                return every
+        return 50
+
+    def tape_forward(self, n_iters: int, checkpoint_every: Optional[int] = None) -> Dict:
         """Runs exactly n_iters iterations from the zero start, recording what
-        the adjoint needs; returns the residual record of the last one."""
+        the adjoint needs; returns the residual record of the last one.
+        checkpoint_every None: checkpoint_interval(n_iters)."""
         torch = self.torch
+        if checkpoint_every is None:
+            checkpoint_every = self.checkpoint_interval(n_iters)
+        self.tape_every = int(checkpoint_every)
         nbytes = c_size_t()
         self._check(self.lib.opf_tape_workspace_size(self.ctx, int(n_iters),
                                                      int(checkpoint_every), byref(nbytes)))

@@ -6,12 +6,14 @@
 // iterations backwards, recomputing from each snapshot which clips were
 // active and applying the transposed piecewise-linear maps:
 //
-//   k_adj_nodeavg  adjoint of the contingency means of W and thetabar that
-//                  the next iteration's device step read (CSR sum per node);
 //   k_adj_sweep    reverse of the node update, the node averages and the line
 //                  prox (the from node of each line stores its adjoint, both
 //                  end nodes accumulate their own side, fixed order, no
-//                  atomics), and the capacity derivative;
+//                  atomics), and the capacity derivative; each node row first
+//                  sums, over the node's devices, the adjoint of the
+//                  contingency means of W and thetabar that the next
+//                  iteration's device step read (for itself and for the far
+//                  node of each line);
 //   k_adj_devices  reverse of the device step: the phase-dual update, the
 //                  generator clip (the generator-limit derivative), the loads
 //                  (the load derivative), and the
@@ -41,8 +43,25 @@ struct NodeAdj {
   R sp[VEC], sb[VEC], u_in[VEC];
 };
 
+// Adjoint of the contingency means of W and thetabar at node n, period t,
+// that the next iteration's device step read: avgW enters each device's prox
+// target with sign -1, avgTB its phase and phase-dual update (sums over the
+// node's devices in CSR order).
+template <typename R>
+__device__ inline void dev_mean_adj(const AdjArgs<R>& a, int n, int t, R& sw, R& st) {
+  const Topo& tp = a.tp;
+  sw = R(0);
+  st = R(0);
+  for (int q = tp.node_nptr[n]; q < tp.node_nptr[n + 1]; ++q) {
+    const int j = tp.node_nterm[q];
+    sw -= a.dev_x[size_t(j) * tp.T + t];
+    st += a.dev_t[size_t(j) * tp.T + t];
+  }
+}
+
+// (mw, mt: dev_mean_adj of the node)
 template <typename R, int VEC>
-__device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, int t, int k0,
+__device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, R mw, R mt, int k0,
                                 NodeAdj<R, VEC>& o) {
   using VR = Vec<R, VEC>;
   const Topo& tp = a.tp;
@@ -50,8 +69,8 @@ __device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, int t, i
   const VR Wb = *reinterpret_cast<const VR*>(a.out.W + off);
   const VR Tb = *reinterpret_cast<const VR*>(a.out.TB + off);
   const R iKp = R(1) / R(tp.Kp);
-  const R aw = a.avw[size_t(n) * tp.T + t] * iKp;
-  const R at = a.avt[size_t(n) * tp.T + t] * iKp;
+  const R aw = mw * iKp;
+  const R at = mt * iKp;
   const R su = R(a.s.su_next);
   const R idg = R(tp.inv_deg[n]);
 #pragma unroll
@@ -68,8 +87,8 @@ __device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, int t, i
 
 // Reverse of one (period, node) row and one 16-byte vector of contingencies.
 template <typename R>
-__device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int q1, R& gsp,
-                               R& gsb) {
+__device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int q1, R mw, R mt,
+                               R& gsp, R& gsb) {
   constexpr int VEC = 16 / sizeof(R);
   using VR = Vec<R, VEC>;
   using VI = Vec<int32_t, VEC>;
@@ -85,7 +104,7 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
   R* tdb_in = a.in.Td + size_t(t) * tp.Kpp + k0;
   const R rp = R(a.s.rp), rt = R(a.s.rt), sv = R(a.s.sv);
   NodeAdj<R, VEC> me;
-  node_adj<R, VEC>(a, off, n, t, k0, me);
+  node_adj<R, VEC>(a, off, n, mw, mt, k0, me);
   R accW[VEC], accB[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) accW[e] = accB[e] = R(0);
@@ -107,7 +126,9 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
                          to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, inv2s, cap, rp, rt, sv, o);
     // (networks of the general line model are rejected by the tape)
     NodeAdj<R, VEC> far;
-    node_adj<R, VEC>(a, oo, m, t, k0, far);
+    R fw, ft;
+    dev_mean_adj<R>(a, m, t, fw, ft);
+    node_adj<R, VEC>(a, oo, m, fw, ft, k0, far);
     const VR Pb = *reinterpret_cast<const VR*>(a.out.P + ol);
     const VR Tmb = *reinterpret_cast<const VR*>(a.out.Tm + ol);
     const VR V1b = *reinterpret_cast<const VR*>(a.out.V1 + ol);
@@ -194,7 +215,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
       t = int(row / a.tp.N);
       n = int(row - int64_t(t) * a.tp.N);
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
-      for (int v = q; v < nv; v += lpr) adj_vec<R>(a, int(row), v, q0, q1, gsp, gsb);
+      R mw, mt;
+      dev_mean_adj<R>(a, n, t, mw, mt);
+      for (int v = q; v < nv; v += lpr) adj_vec<R>(a, int(row), v, q0, q1, mw, mt, gsp, gsb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       gsp += __shfl_xor(gsp, d);
@@ -205,24 +228,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
       a.gsb[size_t(n) * a.tp.T + t] = gsb;
     }
   }
-}
-
-// Adjoint of the node means read by a device step: avgW enters each device's
-// prox target with sign -1, avgTB its phase and phase-dual update.
-template <typename R>
-__global__ void __launch_bounds__(kBlock) k_adj_nodeavg(AdjArgs<R> a) {
-  const Topo& tp = a.tp;
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= int64_t(tp.N) * tp.T) return;
-  const int n = int(i / tp.T), t = int(i - int64_t(n) * tp.T);
-  R sw = R(0), st = R(0);
-  for (int q = tp.node_nptr[n]; q < tp.node_nptr[n + 1]; ++q) {
-    const int j = tp.node_nterm[q];
-    sw -= a.dev_x[size_t(j) * tp.T + t];
-    st += a.dev_t[size_t(j) * tp.T + t];
-  }
-  a.avw[i] = sw;
-  a.avt[i] = st;
 }
 
 // Reverse of the ramp generator's inner ADMM: replays the forward with clip
@@ -540,8 +545,6 @@ __global__ void __launch_bounds__(kBlock) k_copy(CopyList cl) {
 
 template <typename R>
 void launch_adj_iteration(const AdjArgs<R>& a, hipStream_t s) {
-  const int64_t NT = int64_t(a.tp.N) * a.tp.T;
-  k_adj_nodeavg<R><<<int((NT + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
   const int64_t grid = std::min<int64_t>(a.n_grps, 8192);
   k_adj_sweep<R><<<int(grid), kBlock, 0, s>>>(a);
   const int nblk = (a.tp.Jnc + 3) / 4;

@@ -98,7 +98,7 @@ struct TapePlan {
   SnapLayout snap{};
   size_t hist = 0, ckpt = 0, n_ckpt = 0, final_snap = 0, seg = 0;
   size_t adj_line[2][4] = {}, adj_td[2] = {}, adj_node[2][3] = {};
-  size_t gsp = 0, gsb = 0, avw = 0, avt = 0;
+  size_t gsp = 0, gsb = 0;
   size_t dev[5] = {};
   size_t ramp_adj = 0, bat_adj = 0, gcap = 0, gload = 0, gpmax = 0;
   size_t adj_begin = 0, adj_end = 0;
@@ -1238,7 +1238,7 @@ TapePlan plan_tape(const Inst& s, int precision, int M, int C) {
   t.n_ckpt = (size_t(M) + C - 1) / C;
   t.ckpt = L.take(t.snap.total * t.n_ckpt);
   t.final_snap = L.take(t.snap.total);
-  t.seg = L.take(t.snap.total * size_t(C));
+  t.seg = L.take(t.snap.total * size_t(C - 1));  // a segment's iterates after its checkpoint
   t.adj_begin = L.total;
   const size_t line = size_t(s.L) * s.T * s.Kpp * S, node = size_t(s.N) * s.T * s.Kpp * S;
   for (int b = 0; b < 2; ++b) {
@@ -1249,8 +1249,6 @@ TapePlan plan_tape(const Inst& s, int precision, int M, int C) {
   const size_t nt = size_t(s.N) * s.T * S, jt = size_t(s.Jnc) * s.T * S;
   t.gsp = L.take(nt);
   t.gsb = L.take(nt);
-  t.avw = L.take(nt);
-  t.avt = L.take(nt);
   for (int q = 0; q < 5; ++q) t.dev[q] = L.take(jt);
   t.ramp_adj = L.take(4 * size_t(s.nR) * s.T * S);
   t.bat_adj = L.take(6 * size_t(s.B) * s.T * S);
@@ -1289,9 +1287,11 @@ const State<float, float>& inst_state<float>(const Inst& s) {
   return s.st32;
 }
 
-// Copies the iterate (buffer cur) into the snapshot at snap, or back.
+// Copies the iterate (buffer cur) into the snapshot at snap, or back; with
+// ctl_to, the same launch also copies the control block there.
 template <typename R>
-void snapshot(opf_ctx* c, const Inst& s, int cur, char* snap, bool to_snap) {
+void snapshot(opf_ctx* c, const Inst& s, int cur, char* snap, bool to_snap,
+              Ctl* ctl_to = nullptr) {
   char* arr[kSnapArrays];
   state_arrays<R>(inst_state<R>(s), cur, arr);
   CopyList cl{};
@@ -1301,6 +1301,12 @@ void snapshot(opf_ctx* c, const Inst& s, int cur, char* snap, bool to_snap) {
     cl.src[cl.n] = to_snap ? arr[i] : snap + sl.off[i];
     cl.dst[cl.n] = to_snap ? snap + sl.off[i] : arr[i];
     cl.bytes[cl.n] = sl.bytes[i];
+    ++cl.n;
+  }
+  if (ctl_to) {
+    cl.src[cl.n] = reinterpret_cast<const char*>(s.ctl);
+    cl.dst[cl.n] = reinterpret_cast<char*>(ctl_to);
+    cl.bytes[cl.n] = sizeof(Ctl);
     ++cl.n;
   }
   launch_copy(cl, c->stream);
@@ -1349,8 +1355,6 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
   }
   a.gsp = tp(t.gsp);
   a.gsb = tp(t.gsb);
-  a.avw = tp(t.avw);
-  a.avt = tp(t.avt);
   a.dev_p = tp(t.dev[0]);
   a.dev_th = tp(t.dev[1]);
   a.dev_v = tp(t.dev[2]);
@@ -1427,9 +1431,12 @@ opf_status tape_forward(opf_ctx* c, int M, int C, bool warm, int min_iters, int*
   HIP_TRY(c, hipMemcpyAsync(s.ctl, &h0, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
   for (int i = 0; i < M; ++i) {
-    HIP_TRY(c, hipMemcpyAsync(hist + i, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
-    if (i % C == 0)
-      snapshot<R>(c, s, (cur0 + i) & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true);
+    if (i % C == 0)  // the checkpoint and the control block in one copy launch
+      snapshot<R>(c, s, (cur0 + i) & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true,
+                  hist + i);
+    else
+      HIP_TRY(c, hipMemcpyAsync(hist + i, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice,
+                                c->stream));
     enqueue_n(c, 1, false, int64_t(iter0) + i);
   }
   HIP_TRY(c, hipMemcpyAsync(hist + M, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
@@ -1472,15 +1479,23 @@ opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_loa
   Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
   for (int seg = int(t.n_ckpt) - 1; seg >= 0; --seg) {
     const int i0 = seg * C, i1 = std::min(M, i0 + C);
-    // recompute the segment from its checkpoint, keeping every iterate
-    snapshot<R>(c, s, c->tape_hist[i0].cur, tape_ptr(c, t.ckpt + t.snap.total * seg), false);
-    HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + i0, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
-    for (int i = i0; i < i1; ++i) {
-      snapshot<R>(c, s, c->tape_hist[i].cur, tape_ptr(c, t.seg + t.snap.total * (i - i0)), true);
-      if (i + 1 < i1) enqueue_n(c, 1, false, c->tape_hist[i].iter);
+    char* ck = tape_ptr(c, t.ckpt + t.snap.total * seg);
+    // the segment's later iterates, recomputed from its checkpoint (the
+    // reverse reads the first one from the checkpoint itself)
+    auto iterate_at = [&](int i) {
+      return i == i0 ? ck : tape_ptr(c, t.seg + t.snap.total * (i - i0 - 1));
+    };
+    if (i1 - i0 > 1) {
+      snapshot<R>(c, s, c->tape_hist[i0].cur, ck, false);
+      HIP_TRY(c, hipMemcpyAsync(s.ctl, hist + i0, sizeof(Ctl), hipMemcpyDeviceToDevice,
+                                c->stream));
+      for (int i = i0; i + 1 < i1; ++i) {
+        enqueue_n(c, 1, false, c->tape_hist[i].iter);
+        snapshot<R>(c, s, c->tape_hist[i + 1].cur, iterate_at(i + 1), true);
+      }
     }
     for (int i = i1 - 1; i >= i0; --i) {
-      AdjArgs<R> a = adj_args<R>(c, s, tape_ptr(c, t.seg + t.snap.total * (i - i0)), ob, w_obj);
+      AdjArgs<R> a = adj_args<R>(c, s, iterate_at(i), ob, w_obj);
       const Ctl& h = c->tape_hist[i];
       a.s.rp = h.rho_p;
       a.s.rt = h.rho_th;

@@ -95,7 +95,7 @@ struct bf16_t {
 };
 
 // Device control block: penalties, pending dual rescale, counters, flags.
-struct Ctl {
+struct alignas(16) Ctl {  // (16-byte aligned: the tape's copy kernel moves it in 16-byte words)
   double rho_p, rho_th;   // penalties used by the next iteration
   double su, sv;          // pending rescale of U (and inner duals) and of V
   double eps_eff;         // effective tolerance on the RMS residuals
@@ -111,6 +111,7 @@ struct Ctl {
   int32_t precision;      // 0 = FP64, 1 = FP32
   int32_t cur;            // buffer holding the current iterate (0 or 1)
 };
+static_assert(sizeof(Ctl) % 16 == 0, "control blocks are copied in 16-byte words");
 
 // Residual record written by the finalize kernel.
 struct Rec {
@@ -306,8 +307,6 @@ struct AdjArgs {
   AdjBuf<R> out, in;
   R* gsp;      // [N][T] sum over k of the node power-average adjoint (sweep -> devices)
   R* gsb;      // [N][T] same for the phase average
-  R* avw;      // [N][T] adjoint of the contingency means of W read by the next iteration
-  R* avt;      // [N][T] same for thetabar
   R* dev_p;    // [Jnc][T] adjoint carried for the device powers
   R* dev_th;   // [Jnc][T] device phases
   R* dev_v;    // [Jnc][T] contingency-averaged device phase duals

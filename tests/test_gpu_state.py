@@ -80,20 +80,19 @@ def test_export_import_continues_bitwise(split):
 
 def test_warm_start_takes_fewer_iterations():
     """Solve, perturb the loads by a few percent (the next day's forecast),
-    solve again from the previous iterate: fewer iterations than from zero.
-    The tolerance is 1e-3: with two line outages and a device at most nodes
-    this grid's feasible set under the shared device phases of Section 2.3
-    is small, and the oracle itself stalls at an RMS residual of 7.8e-5
-    (above the 1e-4 threshold of 3.6e-5) after 30,000 iterations, while it
-    reaches 1e-3 in 1,189.  Two solves stopped at a relative tolerance of
-    1e-3 agree in objective to that order; tests/test_gpu_warm.py checks
-    the same warm and cold solves against the oracle to 1e-9."""
+    solve again from the previous iterate: fewer iterations than from zero,
+    at a tolerance of 1e-4.  The grid's two outages are lines that a
+    redispatch idles, so the problem is feasible with the device phases
+    shared by all contingencies (Section 2.3; the oracle reaches 1e-4 in
+    2,377 iterations).  Two solves stopped at that relative tolerance agree
+    in objective to 1e-3; tests/test_gpu_warm.py checks the same warm and
+    cold solves against the oracle to 1e-9."""
     from paper_2410_17203_amd.binding import Solver
     say("[state] warm start")
     shape = dict(synth.CONFIGS["tiny"])
     shape["K"] = 2
     inst = synth.make_instance("state", **shape)
-    s = Solver(inst, dtype="f64", eps=1e-3, max_iter=30000)
+    s = Solver(inst, dtype="f64", eps=1e-4, max_iter=30000)
     r0 = s.solve()
     assert r0["status"] == "OPF_OK"
     blob = s.get_state()
@@ -101,16 +100,16 @@ def test_warm_start_takes_fewer_iterations():
     nxt = synth.make_instance("state", **shape)
     rng = np.random.default_rng(1)
     nxt.load_d = np.asarray(inst.load_d) * (1.0 + 0.03 * rng.standard_normal(np.shape(inst.load_d)))
-    cold = Solver(nxt, dtype="f64", eps=1e-3, max_iter=30000)
+    cold = Solver(nxt, dtype="f64", eps=1e-4, max_iter=30000)
     rc = cold.solve()
-    warm = Solver(nxt, dtype="f64", eps=1e-3, max_iter=30000)
+    warm = Solver(nxt, dtype="f64", eps=1e-4, max_iter=30000)
     warm.set_state(blob)
     rw = warm.solve()
     say(f"  cold {rc['iter']} iterations, warm {rw['iter']} (day 1: {r0['iter']})")
     assert rc["status"] == rw["status"] == "OPF_OK"
     assert rw["iter"] < rc["iter"]
     # both stop at the same residual tolerance; their objectives agree to its order
-    assert abs(rw["objective"] - rc["objective"]) <= 5e-3 * abs(rc["objective"])
+    assert abs(rw["objective"] - rc["objective"]) <= 1e-3 * abs(rc["objective"])
     cold.close()
     warm.close()
 
