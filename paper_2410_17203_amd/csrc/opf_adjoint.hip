@@ -16,10 +16,10 @@
 //                  node of each line);
 //   k_adj_devices  reverse of the device step: the phase-dual update, the
 //                  generator clip (the generator-limit derivative), the loads
-//                  (the load derivative), and the
-//                  inner ADMM of ramp generators and batteries replayed with
-//                  recorded clip masks, then reversed through its inner
-//                  iterations (each tridiagonal solve is symmetric, so its
+//                  (the load derivative), and the inner ADMM of ramp
+//                  generators and batteries, reversed through its inner
+//                  iterations with the clip masks the recorded forward run
+//                  kept (each tridiagonal solve is symmetric, so its
 //                  transpose is the same solve).
 //
 // Notation of the forward (per contingency k, period t, line l with from node
@@ -230,21 +230,20 @@ __global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
   }
 }
 
-// Reverse of the ramp generator's inner ADMM: replays the forward with clip
-// masks, then walks the inner iterations backwards.  pb: adjoint of the
-// output power; adj: adjoint of the inner state after the call (read) and
-// before it (written back, lambdas times su).  Returns the adjoint of the
-// prox target X.
+// Reverse of the ramp generator's inner ADMM: walks the inner iterations
+// backwards with the clip masks the recorded forward run kept (masks: this
+// iteration's).  pb: adjoint of the output power; adj: adjoint of the inner
+// state after the call (read) and before it (written back, lambdas times
+// su).  Returns the adjoint of the prox target X.
 template <typename R, int E>
-__device__ void ramp_adj(const Topo& tp, const R* st, R* adj, int r, int g, const R (&X)[E],
-                         R rho_hat, R omega, R su, int n_inner, int lane, const R (&pb)[E],
-                         R (&Xb)[E], double* gpmax) {
+__device__ void ramp_adj(const Topo& tp, const uint32_t* masks, R* adj, int r, int g, R rho_hat,
+                         R omega, R su, int n_inner, int lane, const R (&pb)[E], R (&Xb)[E],
+                         double* gpmax) {
   const int T = tp.T;
   const size_t nRT = size_t(tp.nR) * T;
   const size_t o = size_t(r) * T;
   ClipMasks<E, 2> mk;
-  R pfwd[E];
-  ramp_prox<R, E>(tp, st, nullptr, r, g, X, rho_hat, omega, su, n_inner, lane, pfwd, mk);
+  masks_load<E, 2>(masks + mask_ramp_off(r, E), mk, lane);
   const R c2 = R(tp.gen_c2[g]);
   const R w = R(2) * c2 + rho_hat;
   const R eo = -omega;
@@ -321,16 +320,14 @@ __device__ void ramp_adj(const Topo& tp, const R* st, R* adj, int r, int g, cons
 // Reverse of the battery's inner ADMM; db: adjoint of the discharge delta of
 // the last x-update (the objective's alpha * sum delta), besides pb.
 template <typename R, int E>
-__device__ void battery_adj(const Topo& tp, const R* st, R* adj, int b, const R (&X)[E],
-                            R rho_hat, R omega, R su, int n_inner, int lane, const R (&pb)[E],
-                            R db, R (&Xb)[E]) {
+__device__ void battery_adj(const Topo& tp, const uint32_t* masks, R* adj, int b, R rho_hat,
+                            R omega, R su, int n_inner, int lane, const R (&pb)[E], R db,
+                            R (&Xb)[E]) {
   const int T = tp.T;
   const size_t nBT = size_t(tp.B) * T;
   const size_t o = size_t(b) * T;
   ClipMasks<E, 3> mk;
-  R pfwd[E];
-  double obj = 0.0;
-  battery_prox<R, E>(tp, st, nullptr, b, X, rho_hat, omega, su, n_inner, lane, pfwd, obj, mk);
+  masks_load<E, 3>(masks + mask_bat_off(tp.nR, b, E), mk, lane);
   const BatK<R> k(tp, b, rho_hat, omega);
   const R eo = -k.iw;
   R mul[E], invm[E];
@@ -471,8 +468,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_devices(AdjArgs<R> a) {
         }
       }
     } else {
-      ramp_adj<R, E>(tp, a.ramp_st, a.ramp_adj, r, j, X, rho_hat, omega, su, a.inner_iters, lane,
-                     pb, Xb, a.gpmax);
+      ramp_adj<R, E>(tp, a.masks, a.ramp_adj, r, j, rho_hat, omega, su, a.inner_iters, lane, pb,
+                     Xb, a.gpmax);
     }
   } else if (j < tp.G + tp.D) {
     const int d = j - tp.G;
@@ -484,8 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_devices(AdjArgs<R> a) {
   } else {
     const int b = j - tp.G - tp.D;
     const R db = a.s.last ? R(a.w_obj * tp.bat_alpha[b]) : R(0);
-    battery_adj<R, E>(tp, a.bat_st, a.bat_adj, b, X, rho_hat, omega, su, a.inner_iters, lane, pb,
-                      db, Xb);
+    battery_adj<R, E>(tp, a.masks, a.bat_adj, b, rho_hat, omega, su, a.inner_iters, lane, pb, db,
+                      Xb);
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {

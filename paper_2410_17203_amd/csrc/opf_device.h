@@ -326,6 +326,28 @@ struct ClipMasks {
   __device__ bool at_high(int bound, int it, int e) const { return (high[bound][e] >> it) & 1u; }
 };
 
+template <int E, int NB>
+__device__ inline void masks_store(uint32_t* dst, const ClipMasks<E, NB>& m, int lane) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      dst[((b * 2 + 0) * E + e) * kWave + lane] = m.thru[b][e];
+      dst[((b * 2 + 1) * E + e) * kWave + lane] = m.high[b][e];
+    }
+}
+
+template <int E, int NB>
+__device__ inline void masks_load(const uint32_t* src, ClipMasks<E, NB>& m, int lane) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      m.thru[b][e] = src[((b * 2 + 0) * E + e) * kWave + lane];
+      m.high[b][e] = src[((b * 2 + 1) * E + e) * kWave + lane];
+    }
+}
+
 template <typename R>
 __device__ inline bool clip_pass(R y, R lo, R hi) {
   return !(y < lo) && !(y > hi);

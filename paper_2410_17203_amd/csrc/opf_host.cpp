@@ -97,6 +97,7 @@ struct TapePlan {
   size_t bytes = 0;
   SnapLayout snap{};
   size_t hist = 0, ckpt = 0, n_ckpt = 0, final_snap = 0, seg = 0;
+  size_t masks = 0, mask_words = 0;  // clip masks of every iteration [M][mask_words] (uint32)
   size_t adj_line[2][4] = {}, adj_td[2] = {}, adj_node[2][3] = {};
   size_t gsp = 0, gsb = 0;
   size_t dev[5] = {};
@@ -1239,6 +1240,8 @@ TapePlan plan_tape(const Inst& s, int precision, int M, int C) {
   t.ckpt = L.take(t.snap.total * t.n_ckpt);
   t.final_snap = L.take(t.snap.total);
   t.seg = L.take(t.snap.total * size_t(C - 1));  // a segment's iterates after its checkpoint
+  t.mask_words = mask_words(s.nR, s.B, (s.T + kWave - 1) / kWave);
+  t.masks = L.take(t.mask_words * sizeof(uint32_t) * size_t(M));
   t.adj_begin = L.total;
   const size_t line = size_t(s.L) * s.T * s.Kpp * S, node = size_t(s.N) * s.T * s.Kpp * S;
   for (int b = 0; b < 2; ++b) {
@@ -1430,7 +1433,14 @@ opf_status tape_forward(opf_ctx* c, int M, int C, bool warm, int min_iters, int*
   }
   HIP_TRY(c, hipMemcpyAsync(s.ctl, &h0, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   Ctl* hist = reinterpret_cast<Ctl*>(tape_ptr(c, t.hist));
+  Geom& geo = c->tape.precision == 0 ? c->inst[0].geom64 : c->inst[0].geom32;
+  struct MaskOff {  // later iterations record nothing, however this returns
+    Geom& g;
+    ~MaskOff() { g.mask_rec = nullptr; }
+  } mask_off{geo};
   for (int i = 0; i < M; ++i) {
+    geo.mask_rec = reinterpret_cast<uint32_t*>(
+        tape_ptr(c, t.masks + sizeof(uint32_t) * t.mask_words * size_t(i)));
     if (i % C == 0)  // the checkpoint and the control block in one copy launch
       snapshot<R>(c, s, (cur0 + i) & 1, tape_ptr(c, t.ckpt + t.snap.total * (i / C)), true,
                   hist + i);
@@ -1439,6 +1449,7 @@ opf_status tape_forward(opf_ctx* c, int M, int C, bool warm, int min_iters, int*
                                 c->stream));
     enqueue_n(c, 1, false, int64_t(iter0) + i);
   }
+  geo.mask_rec = nullptr;
   HIP_TRY(c, hipMemcpyAsync(hist + M, s.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->stream));
   c->tape_hist.assign(size_t(M) + 1, Ctl{});
   HIP_TRY(c, hipMemcpyAsync(c->tape_hist.data(), hist, sizeof(Ctl) * (size_t(M) + 1),
@@ -1496,6 +1507,8 @@ opf_status adjoint(opf_ctx* c, const double* cot, double w_obj, double* grad_loa
     }
     for (int i = i1 - 1; i >= i0; --i) {
       AdjArgs<R> a = adj_args<R>(c, s, iterate_at(i), ob, w_obj);
+      a.masks = reinterpret_cast<const uint32_t*>(
+          tape_ptr(c, t.masks + sizeof(uint32_t) * t.mask_words * size_t(i)));
       const Ctl& h = c->tape_hist[i];
       a.s.rp = h.rho_p;
       a.s.rt = h.rho_th;

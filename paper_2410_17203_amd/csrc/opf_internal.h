@@ -209,6 +209,8 @@ struct Geom {
   double* part_nc;        // [n_nc_blocks][2]
   Ctl* ctl;
   Rec* ring;
+  uint32_t* mask_rec = nullptr;  // recorded forward run: where k_devices writes
+                                 // this iteration's clip masks (null: none)
 };
 
 template <typename R, typename VT>
@@ -317,12 +319,23 @@ struct AdjArgs {
   double* gcap;   // [T][L][Kpp] accumulated derivative w.r.t. the line capacities
   double* gload;  // [D][T] accumulated derivative w.r.t. the load demand
   double* gpmax;  // [G][T] accumulated derivative w.r.t. the generator upper limits
+  const uint32_t* masks;  // clip masks the forward recorded for this iteration
   AdjStep s;
   int32_t nv, lanes_per_row, inner_iters;
   int64_t n_grps;
   double omega_scale;
   double w_obj;   // weight of the objective in the cotangent
 };
+
+// Clip masks of the time-coupled devices of one iteration, as a recorded
+// forward run keeps them for the adjoint: per ramp generator r (2 bounds),
+// then per battery b (3 bounds), the words [bound][through, high][e][lane]
+// of its wavefront (E = slots per lane).
+__host__ __device__ inline size_t mask_ramp_off(int r, int E) { return size_t(r) * 4 * E * kWave; }
+__host__ __device__ inline size_t mask_bat_off(int nR, int b, int E) {
+  return size_t(nR) * 4 * E * kWave + size_t(b) * 6 * E * kWave;
+}
+__host__ __device__ inline size_t mask_words(int nR, int B, int E) { return mask_bat_off(nR, B, E); }
 
 // Copy of up to 20 device arrays in one launch (snapshots of the iterate).
 constexpr int kMaxCopy = 20;

@@ -30,8 +30,10 @@ namespace opf {
 
 // Step 2 for one generator, load or battery (one wavefront, all periods):
 // deferred phase-dual update, theta = avg_k(thetabar - v), then the prox of
-// power at target p - avg_k(pbar + u) with penalty (K+1) rho_p.
-template <typename R, typename VT, int E>
+// power at target p - avg_k(pbar + u) with penalty (K+1) rho_p.  REC: also
+// write the clip masks of the time-coupled prox to a.g.mask_rec (a recorded
+// forward run, for the adjoint).
+template <typename R, typename VT, int E, bool REC = false>
 __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R rho_hat,
                           double& acc_dp, double& acc_obj) {
   const Topo& tp = a.tp;
@@ -66,6 +68,11 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
           pn[e] = clampv(gen_target(X[e], c1, c2, rho_hat), R(tp.gen_pmin[size_t(j) * T + t]),
                          R(tp.gen_pmax[size_t(j) * T + t]));
       }
+    } else if constexpr (REC) {
+      ClipMasks<E, 2> mk;
+      ramp_prox<R, E>(tp, a.st.ramp_st, a.st.ramp_st, r, j, X, rho_hat, omega, su, a.g.inner_iters,
+                      lane, pn, mk);
+      masks_store<E, 2>(a.g.mask_rec + mask_ramp_off(r, E), mk, lane);
     } else {
       NoMasks nm;
       ramp_prox<R, E>(tp, a.st.ramp_st, a.st.ramp_st, r, j, X, rho_hat, omega, su, a.g.inner_iters,
@@ -81,6 +88,12 @@ __device__ void nc_device(const KArgs<R, VT>& a, int j, int lane, R su, R sv, R 
       const int t = lane * E + e;
       if (t < T) pn[e] = -R(tp.load_d[size_t(d) * T + t]);
     }
+  } else if constexpr (REC) {
+    const int b = j - tp.G - tp.D;
+    ClipMasks<E, 3> mk;
+    battery_prox<R, E>(tp, a.st.bat_st, a.st.bat_st, b, X, rho_hat, omega, su, a.g.inner_iters,
+                       lane, pn, obj, mk);
+    masks_store<E, 3>(a.g.mask_rec + mask_bat_off(tp.nR, b, E), mk, lane);
   } else {
     NoMasks nm;
     battery_prox<R, E>(tp, a.st.bat_st, a.st.bat_st, j - tp.G - tp.D, X, rho_hat, omega, su,
@@ -713,7 +726,7 @@ k_sweep_tile(KArgs<R, VT> a) {
 }
 
 // Step 2 for all generators, loads and batteries, one per wavefront.
-template <typename R, typename VT, int E>
+template <typename R, typename VT, int E, bool REC>
 __global__ void __launch_bounds__(kBlock) k_devices(KArgs<R, VT> a) {
   Ctl* ctl = a.g.ctl;
   if (ctl->done) return;
@@ -722,7 +735,7 @@ __global__ void __launch_bounds__(kBlock) k_devices(KArgs<R, VT> a) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = blockIdx.x * (kBlock / kWave) + w;
   double dp = 0.0, ob = 0.0;
-  if (j < a.tp.Jnc) nc_device<R, VT, E>(a, j, lane, su, sv, R(a.tp.Kp) * rp, dp, ob);
+  if (j < a.tp.Jnc) nc_device<R, VT, E, REC>(a, j, lane, su, sv, R(a.tp.Kp) * rp, dp, ob);
   dp = block_sum(dp, sh);
   ob = block_sum(ob, sh);
   if (threadIdx.x == 0) {
@@ -1134,11 +1147,21 @@ template <typename R, typename VT>
 void launch_devices(const KArgs<R, VT>& a, hipStream_t s) {
   if (a.g.n_nc_blocks == 0) return;
   const int E = (a.tp.T + kWave - 1) / kWave;
+  const dim3 grid(a.g.n_nc_blocks);
+  if (a.g.mask_rec) {
+    switch (E) {
+      case 1: k_devices<R, VT, 1, true><<<grid, kBlock, 0, s>>>(a); break;
+      case 2: k_devices<R, VT, 2, true><<<grid, kBlock, 0, s>>>(a); break;
+      case 3: k_devices<R, VT, 3, true><<<grid, kBlock, 0, s>>>(a); break;
+      default: k_devices<R, VT, 4, true><<<grid, kBlock, 0, s>>>(a); break;
+    }
+    return;
+  }
   switch (E) {
-    case 1: k_devices<R, VT, 1><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
-    case 2: k_devices<R, VT, 2><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
-    case 3: k_devices<R, VT, 3><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
-    default: k_devices<R, VT, 4><<<a.g.n_nc_blocks, kBlock, 0, s>>>(a); break;
+    case 1: k_devices<R, VT, 1, false><<<grid, kBlock, 0, s>>>(a); break;
+    case 2: k_devices<R, VT, 2, false><<<grid, kBlock, 0, s>>>(a); break;
+    case 3: k_devices<R, VT, 3, false><<<grid, kBlock, 0, s>>>(a); break;
+    default: k_devices<R, VT, 4, false><<<grid, kBlock, 0, s>>>(a); break;
   }
 }
 
