@@ -614,64 +614,51 @@ __device__ __forceinline__ void line_prox(const Vec<R, VEC>& P, const Vec<R, VEC
 // 2.1: lossless transfer within cap, no phase relation).  hold: the stored
 // half phase difference where it is not P/(2s) (modes 1 and 2); z: index of
 // a change that takes the line out, whose half difference lives in Tz.
-template <typename R, int VEC>
-struct LinePar {
-  R s[VEC], cap[VEC], hold[VEC];
-  int mode[VEC];
-  int z[VEC];
-};
-
-// Base parameters, the N-1 outage (ok), and the line's changes (CSR entries
-// ordered by contingency) for contingencies k0 .. k0+VEC-1.  dci >= 0 marks
-// a DC link (Hd: its stored half differences; a change sets its capacity).
-template <typename R, int VEC>
-__device__ inline void line_params(const Topo& tp, int l, int k0, const Vec<int32_t, VEC>& ok,
-                                   int dci, const Vec<R, VEC>& Hd, const R* td_old,
-                                   const R* tz_old, LinePar<R, VEC>& q) {
-  const R s = R(tp.sus[l]), cap = R(tp.cap[l]);
+// line_prox with per-contingency parameters (the general line model).  The
+// parameters of contingency k0+e are formed in the loop: the base values,
+// the N-1 outage (ok), a DC link (dci >= 0; Hd: its stored half
+// differences), then the line's changes (CSR entries ordered by
+// contingency: a change sets a DC link's capacity, takes an AC line out
+// (its stored half difference in tz_old[z]) or sets its susceptance and
+// capacity).  td_old: the outaged lines' half differences for k0 ...
+// k0+VEC-1.  With tz_new, the new half difference of a line a change takes
+// out is stored at tz_new[z].
+template <typename R, typename VT, int VEC>
+__device__ __forceinline__ void line_prox_gen(const Topo& tp, int l, int k0,
+                                              const Vec<int32_t, VEC>& ok, int dci,
+                                              const Vec<R, VEC>& Hd, const R* td_old,
+                                              const R* tz_old, R* tz_new, const Vec<R, VEC>& P,
+                                              const Vec<R, VEC>& Tm, const Vec<VT, VEC>& V1,
+                                              const Vec<VT, VEC>& V2, const Vec<R, VEC>& Wf,
+                                              const Vec<R, VEC>& Wh, const Vec<R, VEC>& Bf,
+                                              const Vec<R, VEC>& Bh, int Kp, R rp, R rt, R sv,
+                                              LineOut<R, VEC>& o) {
+  const R s0 = R(tp.sus[l]), cap0 = R(tp.cap[l]);
+  const int c0 = tp.chg_ptr[l], c1 = tp.chg_ptr[l + 1];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) {
+    const int k = k0 + e;
     const bool outg = ok.x[e] == l;
-    q.s[e] = s;  // (changes below may replace it; line_prox_gen forms 1 / (2s))
-    q.cap[e] = cap;
-    q.z[e] = -1;
-    q.mode[e] = outg ? 1 : (dci >= 0 ? 2 : 0);
-    q.hold[e] = dci >= 0 ? Hd.x[e] : (outg ? td_old[e] : R(0));
-  }
-  const int c1 = tp.chg_ptr[l + 1];
-  for (int c = tp.chg_ptr[l]; c < c1; ++c) {
-    const LineChg ch = tp.chg[c];
-    if (ch.k >= k0 + VEC) break;
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      if (ch.k != k0 + e) continue;
+    R sus = s0, cap = cap0;
+    int mode = outg ? 1 : (dci >= 0 ? 2 : 0), z = -1;
+    R hold = dci >= 0 ? Hd.x[e] : (outg ? td_old[e] : R(0));
+    for (int c = c0; c < c1; ++c) {
+      const LineChg ch = tp.chg[c];
+      if (ch.k > k) break;
+      if (ch.k != k) continue;
       if (dci >= 0) {
-        q.cap[e] = R(ch.cap);
+        cap = R(ch.cap);
       } else if (ch.z >= 0) {
-        q.mode[e] = 1;
-        q.z[e] = ch.z;
-        q.hold[e] = tz_old[ch.z];
+        mode = 1;
+        z = ch.z;
+        hold = tz_old[ch.z];
       } else {
-        q.s[e] = R(ch.sus);
-        q.cap[e] = R(ch.cap);
+        sus = R(ch.sus);
+        cap = R(ch.cap);
       }
     }
-  }
-}
-
-// line_prox with per-contingency parameters (the general line model).
-template <typename R, typename VT, int VEC>
-__device__ __forceinline__ void line_prox_gen(const Vec<R, VEC>& P, const Vec<R, VEC>& Tm,
-                                              const Vec<VT, VEC>& V1, const Vec<VT, VEC>& V2,
-                                              const Vec<R, VEC>& Wf, const Vec<R, VEC>& Wh,
-                                              const Vec<R, VEC>& Bf, const Vec<R, VEC>& Bh,
-                                              const LinePar<R, VEC>& q, int k0, int Kp, R rp,
-                                              R rt, R sv, LineOut<R, VEC>& o) {
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) {
-    const int mode = q.mode[e];
-    const R inv2s = R(0.5) / (mode == 0 ? q.s[e] : R(1));
-    const R half = mode == 0 ? P.x[e] * inv2s : q.hold[e];
+    const R inv2s = R(0.5) / (mode == 0 ? sus : R(1));
+    const R half = mode == 0 ? P.x[e] * inv2s : hold;
     const R th1 = Tm.x[e] + half, th2 = Tm.x[e] - half;
     R v1 = sv * (DIO<VT, R>::in(V1.x[e]) + th1 - Bf.x[e]);
     R v2 = sv * (DIO<VT, R>::in(V2.x[e]) + th2 - Bh.x[e]);
@@ -685,16 +672,17 @@ __device__ __forceinline__ void line_prox_gen(const Vec<R, VEC>& P, const Vec<R,
       hn = R(0.5) * (xi1 - xi2);
     } else if (mode == 2) {  // HVDC link: flow at the clipped midpoint, phases at their targets
       u = R(0.5) * (z2 - z1);
-      pn = clampv(u, -q.cap[e], q.cap[e]);
+      pn = clampv(u, -cap, cap);
       hn = R(0.5) * (xi1 - xi2);
     } else {
       const R iden = R(1) / (R(2) * rp + R(2) * rt * inv2s * inv2s);
       const R ca = rp * iden, cb = rt * inv2s * iden;
       u = ca * (z2 - z1) + cb * (xi1 - xi2);
-      pn = clampv(u, -q.cap[e], q.cap[e]);
+      pn = clampv(u, -cap, cap);
       hn = pn * inv2s;
     }
-    if (k0 + e >= Kp) pn = tm = v1 = v2 = hn = R(0);
+    if (k >= Kp) pn = tm = v1 = v2 = hn = R(0);
+    if (tz_new && z >= 0) tz_new[z] = hn;
     o.p[e] = pn;
     o.tm[e] = tm;
     o.v1[e] = v1;

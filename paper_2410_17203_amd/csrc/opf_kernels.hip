@@ -24,6 +24,8 @@
 //
 // The path is sparse and elementwise (no dense contraction), so it runs on
 // the vector ALUs and is bound by HBM bandwidth.
+#include <type_traits>
+
 #include "opf_device.h"
 
 namespace opf {
@@ -175,7 +177,6 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
       LineOut<R, VEC> o;
       int dci = -1;
       size_t oh = 0;
-      LinePar<R, VEC> lp;
       // general line model: only DC links and lines with changes need
       // per-contingency parameters; the others take the N-1 prox
       bool special = false;
@@ -187,10 +188,12 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
         oh = dci >= 0 ? ck_off(t, dci, k0, tp.Ldc, tp.Kpp) : 0;
         VR Hx{};
         if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
-        line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old, A.Tz + size_t(t) * tp.Zc, lp);
-        line_prox_gen<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo,
-                                  to_end ? Wo : Wx[u], to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], lp,
-                                  k0, tp.Kp, rp, rt, sv, o);
+        // (the from node stores the line, and the half differences of the
+        // lines its changes take out)
+        line_prox_gen<R, VT, VEC>(tp, l, k0, ok, dci, Hx, td_old, A.Tz + size_t(t) * tp.Zc,
+                                  to_end ? nullptr : B.Tz + size_t(t) * tp.Zc, P[u], Tm[u],
+                                  V1[u], V2[u], to_end ? Wx[u] : Wo, to_end ? Wo : Wx[u],
+                                  to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], tp.Kp, rp, rt, sv, o);
       } else {
         line_prox<R, VT, VEC>(P[u], Tm[u], V1[u], V2[u], to_end ? Wx[u] : Wo,
                               to_end ? Wo : Wx[u], to_end ? Bx[u] : Bo, to_end ? Bo : Bx[u], ok, l,
@@ -215,16 +218,11 @@ __device__ inline void sweep_vec(const KArgs<R, VT>& a, const Buf<R, VT>& A, con
         st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
         st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
         st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-        if (special) {
-          if (dci >= 0) {
-            VR Hn;
+        if (special && dci >= 0) {
+          VR Hn;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) Hn.x[e] = o.half[e];
-            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
-          }
-#pragma unroll
-          for (int e = 0; e < VEC; ++e)
-            if (lp.z[e] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[e]] = o.half[e];
+          for (int e = 0; e < VEC; ++e) Hn.x[e] = o.half[e];
+          *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
         }
       }
 #pragma unroll
@@ -400,7 +398,26 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
   const int T = tp.T, N = tp.N, L = tp.L, Kpp = tp.Kpp;
   const int n0 = tp.clus_n0[cq], cn = tp.clus_n0[cq + 1] - n0;
   const int j0 = tp.tl_ptr[cq], nl = tp.tl_ptr[cq + 1] - j0;
-  for (int j = threadIdx.x; j < nl; j += kTileBlock) sTl[j] = tp.tl[j0 + j];
+  // general line model: which of the cluster's lines need per-contingency
+  // parameters (a DC link or a line with changes), one bit per line (thread
+  // j stages line j), and whether any does
+  // (read after the first pass's barrier)
+  static_assert(kTileLines <= kTileBlock, "one staged line per thread");
+  constexpr int kSpecWords = (kTileLines + kWave - 1) / kWave;
+  __shared__ uint64_t sSpec[GEN ? kSpecWords : 1];
+  {
+    bool sp = false;
+    if (int(threadIdx.x) < nl) {
+      const int4 e = tp.tl[j0 + threadIdx.x];
+      sTl[threadIdx.x] = e;
+      if constexpr (GEN) sp = tp.line_dc[e.x] >= 0 || tp.chg_ptr[e.x] != tp.chg_ptr[e.x + 1];
+    }
+    if constexpr (GEN) {
+      const uint64_t m = __ballot(sp);
+      if ((threadIdx.x & (kWave - 1)) == 0 && int(threadIdx.x) < kTileLines)
+        sSpec[threadIdx.x / kWave] = m;
+    }
+  }
   const int lp0 = tp.node_lptr[n0], np0 = tp.node_nptr[n0];
   const int nlt = tp.node_lptr[n0 + cn] - lp0;  // <= 2 kTileLines (each line has two ends)
   const int ndt = tp.node_nptr[n0 + cn] - np0;  // <= kTileDev
@@ -489,7 +506,13 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
         pU = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(A.U + on));
       }
       lds_barrier();
-      for (int x = threadIdx.x; x < nl * nvt; x += kTileBlock) {
+      // One line vector of the pass: line j of the cluster, vector u of its
+      // row.  SPECIAL: a line of the general line model that needs
+      // per-contingency parameters (a DC link or a line with changes).  The
+      // general variant takes those lines in a loop of their own, after the
+      // others, so the registers of that code do not weigh on the main loop.
+      auto line_item = [&](int x, auto special_tag) {
+        constexpr bool SPECIAL = decltype(special_tag)::value;
         const int j = int((uint32_t(x) * nvt_mag) >> 16), u = x - j * nvt;
         const int p = int((uint32_t(u) * nvc_mag) >> 16), v = u - p * nvc;
         const int t = tg + p;
@@ -525,19 +548,16 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
         LineOut<R, VEC> o;
         int dci = -1;
         size_t oh = 0;
-        LinePar<R, VEC> lp;
-        bool special = false;  // as in the node-row sweep
-        if constexpr (GEN) {
+        if constexpr (SPECIAL) {
           dci = tp.line_dc[l];
-          special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
-        }
-        if (special) {
           oh = dci >= 0 ? (size_t(t) * Kpp + c0) * tp.Ldc + (s0 - c0) + size_t(dci) * w + v * VEC
                         : 0;
           VR Hx{};
           if (dci >= 0) Hx = *reinterpret_cast<const VR*>(A.Hd + oh);
-          line_params<R, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0, A.Tz + size_t(t) * tp.Zc, lp);
-          line_prox_gen<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, lp, k0, tp.Kp, rp, rt, sv, o);
+          line_prox_gen<R, VT, VEC>(tp, l, k0, ok, dci, Hx, td_old + k0,
+                                    A.Tz + size_t(t) * tp.Zc,
+                                    e.y >= 0 ? B.Tz + size_t(t) * tp.Zc : nullptr, P, Tm, V1, V2,
+                                    Wf, Wh, Bf, Bh, tp.Kp, rp, rt, sv, o);
         } else {
           line_prox<R, VT, VEC>(P, Tm, V1, V2, Wf, Wh, Bf, Bh, ok, l, td_old + k0, k0, tp.Kp,
                                 R(tp.hinv_sus[l]), R(tp.cap[l]), rp, rt, sv, o);
@@ -561,16 +581,11 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
           st_stream(reinterpret_cast<VR*>(B.Tm + ol), Tn);
           st_stream(reinterpret_cast<VV*>(B.V1 + ol), V1n);
           st_stream(reinterpret_cast<VV*>(B.V2 + ol), V2n);
-          if (special) {
-            if (dci >= 0) {
-              VR Hn;
+          if (SPECIAL && dci >= 0) {
+            VR Hn;
 #pragma unroll
-              for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
-              *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
-            }
-#pragma unroll
-            for (int q = 0; q < VEC; ++q)
-              if (lp.z[q] >= 0) B.Tz[size_t(t) * tp.Zc + lp.z[q]] = o.half[q];
+            for (int q = 0; q < VEC; ++q) Hn.x[q] = o.half[q];
+            *reinterpret_cast<VR*>(B.Hd + oh) = Hn;
           }
         }
         VR Po, To, Ho;
@@ -583,6 +598,26 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
         *reinterpret_cast<VR*>(sP + j * SUB + u * VEC) = Po;
         *reinterpret_cast<VR*>(sTm + j * SUB + u * VEC) = To;
         *reinterpret_cast<VR*>(sH + j * SUB + u * VEC) = Ho;
+      };
+      auto is_special = [&](int x) {
+        const int j = int((uint32_t(x) * nvt_mag) >> 16);
+        return ((sSpec[j / kWave] >> (j & (kWave - 1))) & 1ull) != 0;
+      };
+      bool any_spec = false;
+      if constexpr (GEN) {
+#pragma unroll
+        for (int q = 0; q < kSpecWords; ++q) any_spec = any_spec || sSpec[q] != 0ull;
+      }
+      for (int x = threadIdx.x; x < nl * nvt; x += kTileBlock) {
+        if constexpr (GEN) {
+          if (any_spec && is_special(x)) continue;
+        }
+        line_item(x, std::false_type{});
+      }
+      if constexpr (GEN) {
+        if (any_spec)
+          for (int x = threadIdx.x; x < nl * nvt; x += kTileBlock)
+            if (is_special(x)) line_item(x, std::true_type{});
       }
       {  // node rows of the next pass, or of the next group's first pass,
          // in flight during phase 2
