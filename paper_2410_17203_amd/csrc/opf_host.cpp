@@ -147,6 +147,7 @@ struct opf_ctx {
   int64_t* d_grp32 = nullptr;
   int64_t* d_tiles64 = nullptr;
   int64_t* d_tiles32 = nullptr;
+  int32_t* d_queue = nullptr;  // work counters of the batched tiled sweep (zero at load)
   // launch tuning
   int lanes_shift = 0;       // lanes per row = natural value << shift (or >>)
   double grid_factor = 1.0;  // sweep grid = resident blocks * factor
@@ -503,7 +504,7 @@ void plan_instance(const opf_ctx* c, const Inst& s, Layout& L, InstPlan& p) {
 }
 
 struct BatchPlan {
-  size_t descs64, descs32, dev_prefix, grp64, grp32, tiles64, tiles32;
+  size_t descs64, descs32, dev_prefix, grp64, grp32, tiles64, tiles32, queue;
 };
 
 void plan_batch(int count, Layout& L, BatchPlan& b) {
@@ -514,6 +515,7 @@ void plan_batch(int count, Layout& L, BatchPlan& b) {
   b.grp32 = L.take(sizeof(int64_t) * (count + 1));
   b.tiles64 = L.take(sizeof(int64_t) * (count + 1));
   b.tiles32 = L.take(sizeof(int64_t) * (count + 1));
+  b.queue = L.take(sizeof(int32_t) * 8);
 }
 
 template <typename R, typename VT>
@@ -762,6 +764,7 @@ opf_status refresh_geometry(opf_ctx* c) {
     t.n_sweep_blocks = nb;
     t.tile_prefix = d_tiles;
     t.total_tiles = tiles[n];
+    t.tile_queue = c->d_queue;
     {
       double total = 0.0;
       for (int i = 0; i < n; ++i) total += cost[i] * double(tiles[i + 1] - tiles[i]);
@@ -1151,6 +1154,7 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
     c->d_grp32 = reinterpret_cast<int64_t*>(c->ws + bp.grp32);
     c->d_tiles64 = reinterpret_cast<int64_t*>(c->ws + bp.tiles64);
     c->d_tiles32 = reinterpret_cast<int64_t*>(c->ws + bp.tiles32);
+    c->d_queue = reinterpret_cast<int32_t*>(c->ws + bp.queue);
   }
   s = refresh_geometry(c);
   if (s != OPF_OK) return s;

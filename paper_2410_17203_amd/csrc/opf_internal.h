@@ -234,6 +234,8 @@ struct BatchTab {
   const int64_t* tile_prefix; // [n_inst + 1] prefix of the work items (runs x clusters)
   int64_t total_tiles;
   int64_t xcd_bounds[9];      // the work list split into 8 XCD ranges of equal estimated work
+  int32_t* tile_queue;        // [8] items taken from each XCD range in this launch (zeroed
+                              // by k_finalize_batch after every launch)
   int64_t total_dev;
   int64_t total_grps;
 };

@@ -363,7 +363,8 @@ __global__ void __launch_bounds__(kBlock) OPF_SWEEP_ATTR k_sweep(KArgs<R, VT> a)
 template <typename R, typename VT, bool GEN>
 __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>& A,
                                          const Buf<R, VT>& B, int cq, int t0, int t1, R rp, R rt,
-                                         R sv, bool check, double (&acc)[5]) {
+                                         R sv, bool check, double (&acc)[5],
+                                         double* item_part = nullptr) {
   constexpr int VEC = 16 / sizeof(R);
   // contingencies per pass: 128 bytes of each row (a chunk in FP32, half a
   // chunk in FP64), so that the LDS footprint is the same in both precisions
@@ -728,6 +729,27 @@ __device__ __forceinline__ void tile_run(const KArgs<R, VT>& a, const Buf<R, VT>
       a.st.avgTB[o] = R(ab / double(tp.Kp));
     }
   }
+  if (item_part) {  // this item's residual partials: each wave's sums, then the waves in order
+    // (in sP, whose last reads were in the node phase, before the barrier above)
+    constexpr int kWaves = kTileBlock / kWave;
+    static_assert(5 * kWaves * sizeof(double) <= sizeof(sP), "wave sums fit in sP");
+    double* const scr = reinterpret_cast<double*>(sP);
+    double ws[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ws[k] = wave_sum(acc[k]);
+      acc[k] = 0.0;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) scr[(threadIdx.x / kWave) * 5 + k] = ws[k];
+    lds_barrier();
+    if (threadIdx.x < 5) {
+      double v = 0.0;
+      for (int w = 0; w < kWaves; ++w) v += scr[w * 5 + threadIdx.x];
+      item_part[threadIdx.x] = v;
+    }
+  }
 }
 
 // (4 waves per SIMD: two workgroups per CU, the most its LDS footprint allows)
@@ -1010,49 +1032,46 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
   }
 }
 
-// Tiled sweep over the tiles of all instances of a batch (one work list, in
-// instance order).  A workgroup's tiles of one instance are consecutive in
-// its own sequence, so it writes that instance's residual partials once, in
-// its own slot.  It zeroes its slot of every instance it does not visit:
-// those before its first tile, between two instances it visits (a small
-// instance can fall entirely inside one stride of its sequence) and after
-// its last tile, so no slot keeps a value from an earlier launch of another
-// grid size.
+// Tiled sweep over the work items of all instances of a batch (one work
+// list, in instance order).  Items are handed out as the workgroups free
+// up: each XCD's range of the list (split by estimated work) has a counter,
+// a workgroup takes the next item of its own XCD's range and, once that
+// range is used up, of the other ranges in turn, so the workgroups finish
+// together whatever the sizes of their items.  An item writes its own FP64
+// residual partials (each wave's sums, then the waves in order) to its
+// instance's slot for that item, so the reduction order does not depend on
+// which workgroup ran the item.  The counters are reset to zero by
+// k_finalize_batch, which follows every launch of this kernel.
 template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_tile_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
-  __shared__ double sh[kTileBlock / kWave];
-  // XCD ranges of the work list split by estimated work, not by count
-  const int x = blockIdx.x & 7, per = gridDim.x >> 3;
-  Sweep sweep;
-  sweep.first = tab.xcd_bounds[x] + (blockIdx.x >> 3);
-  sweep.end = tab.xcd_bounds[x + 1];
-  sweep.step = per;
+  __shared__ int64_t sItem[2];  // the next item, double-buffered by parity
+  const int x0 = blockIdx.x & 7;
+  int xs = 0;  // (thread 0) ranges used up so far, own range first
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  int cur_i = -1;
-  auto flush = [&](int i) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double v = block_sum<kTileBlock>(acc[k], sh);
-      if (threadIdx.x == 0) descs[i].g.part_sweep[5 * blockIdx.x + k] = v;
-      acc[k] = 0.0;
+  for (int n = 0;; ++n) {
+    if (threadIdx.x == 0) {
+      int64_t g = -1;
+      for (; xs < 8; ++xs) {
+        const int x = (x0 + xs) & 7;
+        const int64_t c = tab.xcd_bounds[x] + int64_t(atomicAdd(tab.tile_queue + x, 1));
+        if (c < tab.xcd_bounds[x + 1]) {
+          g = c;
+          break;
+        }
+      }
+      sItem[n & 1] = g;
     }
-  };
-  // zeroes this workgroup's slot of the instances lo < i < hi
-  auto zero_between = [&](int lo, int hi) {
-    for (int q = threadIdx.x; q < 5 * (hi - lo - 1); q += kTileBlock) {
-      const int i = lo + 1 + q / 5;
-      descs[i].g.part_sweep[5 * blockIdx.x + (q - 5 * (i - lo - 1))] = 0.0;
-    }
-  };
-  for (int64_t g = sweep.first; g < sweep.end; g += sweep.step) {
+    lds_barrier();
+    // (the same value in every lane: made a scalar so that the instance's
+    // descriptor is read through the scalar unit, as with a computed index)
+    const int64_t gl = sItem[n & 1];
+    const int64_t g = int64_t(
+        (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint64_t(gl) >> 32)))) << 32) |
+        uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(gl)))))));
+    if (g < 0) break;
     const int i = find_inst(tab.tile_prefix, tab.n_inst, g);
-    if (i != cur_i) {
-      if (cur_i >= 0) flush(cur_i);
-      zero_between(cur_i, i);
-      cur_i = i;
-    }
     const KArgs<R, VT>& a = descs[i];
     Ctl* ctl = a.g.ctl;
     if (ctl->done) continue;
@@ -1063,18 +1082,21 @@ k_sweep_tile_batch(BatchTab tab) {
     const int r = int(li / a.tp.Q), cq = int(li - int64_t(r) * a.tp.Q);
     const int t0 = r * a.g.tile_run;
     tile_run<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], cq, t0,
-                         min(a.tp.T, t0 + a.g.tile_run), rp, rt, sv, check, acc);
+                         min(a.tp.T, t0 + a.g.tile_run), rp, rt, sv, check, acc,
+                         check ? a.g.part_sweep + 5 * li : nullptr);
   }
-  if (cur_i >= 0) flush(cur_i);
-  zero_between(cur_i, tab.n_inst);
 }
 
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
   const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
   const KArgs<R, VT>& a = descs[blockIdx.x];
+  // the tiled sweep's work counters start the next launch at zero
+  if (blockIdx.x == 0 && threadIdx.x < 8) tab.tile_queue[threadIdx.x] = 0;
   const int64_t ng = tab.grp_prefix[blockIdx.x + 1] - tab.grp_prefix[blockIdx.x];
-  const int n_sweep = tab.tile_blocks > 0 ? tab.tile_blocks : int(ng * (kBlock / kWave));
+  // partials: one per work item of the tiled sweep, else per (row group, wavefront)
+  const int64_t n_items = tab.tile_prefix[blockIdx.x + 1] - tab.tile_prefix[blockIdx.x];
+  const int n_sweep = tab.tile_blocks > 0 ? int(n_items) : int(ng * (kBlock / kWave));
   finalize_body(a, n_sweep, a.tp.Jnc);
 }
 
