@@ -287,7 +287,8 @@ typedef struct {
  * loaded instance(s), for one instance or a batch: the node-row sweep with
  * lanes per row halved/natural/doubled x sweep grid 0.5/1/2 times the
  * resident blocks, and, where every instance has clusters, the tiled sweep
- * with 1, 2 or 4 period groups per work item x grid 0.5/1/2; keeps the
+ * with 1, 2, 4 or 8 period groups per work item x grid 0.5/1/2 (untuned
+ * defaults: 1 for one instance, 4 for a batch); keeps the
  * fastest and resets the iterate to the zero start.  With cache_path
  * non-NULL, a result for the same device, precision and instance shapes is
  * read from that text file (one line per result: key, lanes shift, grid

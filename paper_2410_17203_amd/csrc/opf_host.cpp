@@ -1136,6 +1136,10 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
   c->ws = static_cast<char*>(d_ws);
   c->ws_bytes = bytes;
   c->batch = count > 1;
+  // a batch's work items default to four period groups (each handed out as
+  // a workgroup frees up; measured best on the uneven 64-instance batch),
+  // one instance's to one; opf_autotune picks from 1, 2, 4, 8
+  c->tile_groups = c->batch ? 4 : 1;
   HIP_TRY(c, hipMemsetAsync(c->ws, 0, lay.total, c->stream));
   c->max_T = 1;
   for (int i = 0; i < count; ++i) {
@@ -2008,7 +2012,7 @@ opf_status opf_autotune(opf_ctx* c, int32_t trials, const char* cache_path, opf_
     for (int shift = -1; shift <= 1; ++shift)
       for (double gf : {0.5, 1.0, 2.0}) cands.push_back({0, shift, 1, gf});
     if (tiles_possible)
-      for (int groups : {1, 2, 4})
+      for (int groups : {1, 2, 4, 8})
         for (double gf : {0.5, 1.0, 2.0}) cands.push_back({1, 0, groups, gf});
     for (const Cand& cd : cands) {
       const int shift = cd.shift;
