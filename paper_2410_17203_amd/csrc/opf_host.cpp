@@ -169,6 +169,8 @@ struct opf_ctx {
   // record of a forward run for the adjoint
   TapePlan tape{};
   std::vector<Ctl> tape_hist;
+  // batch instances left out of the work lists (stopped ones, while opf_solve runs)
+  std::vector<char> retired;
 };
 
 namespace {
@@ -712,16 +714,18 @@ opf_status refresh_geometry(opf_ctx* c) {
   std::vector<KArgs<float, bf16_t>> d32b(n);
   for (int i = 0; i < n; ++i) {
     const Inst& s = c->inst[i];
-    dev[i + 1] = dev[i] + s.Jnc;
-    g64[i + 1] = g64[i] + s.geom64.n_grps;
-    g32[i + 1] = g32[i] + s.geom32.n_grps;
-    const int64_t Q = s.topo.Q;
+    // a retired instance has no work items, device waves or row groups
+    const int64_t on = (size_t(i) < c->retired.size() && c->retired[i]) ? 0 : 1;
+    dev[i + 1] = dev[i] + on * s.Jnc;
+    g64[i + 1] = g64[i] + on * s.geom64.n_grps;
+    g32[i + 1] = g32[i] + on * s.geom32.n_grps;
+    const int64_t Q = on * s.topo.Q;
     tiles64[i + 1] = tiles64[i] + int64_t((s.T + s.geom64.tile_run - 1) / s.geom64.tile_run) * Q;
     tiles32[i + 1] = tiles32[i] + int64_t((s.T + s.geom32.tile_run - 1) / s.geom32.tile_run) * Q;
     const double per_period = Q > 0 ? double(2 * s.L + s.N) / double(Q) * s.Kpp : 0.0;
     cost64[i] = per_period * s.geom64.tile_run + 4096.0;
     cost32[i] = per_period * s.geom32.tile_run + 4096.0;
-    all_tiles = all_tiles && s.topo.Q > 0;
+    all_tiles = all_tiles && s.topo.Q > 0;  // (of every instance, retired or not)
     d64[i] = kargs(s, s.st64, s.geom64);
     d32[i] = kargs(s, s.st32, s.geom32);
     d32b[i] = kargs(s, s.st32b, s.geom32);
@@ -792,6 +796,21 @@ opf_status refresh_geometry(opf_ctx* c) {
   tab(c->tab64, c->d_descs64, c->d_grp64, g64[n], res64, tile64, c->d_tiles64, tiles64, cost64);
   tab(c->tab32, c->d_descs32, c->d_grp32, g32[n], res32, tile32, c->d_tiles32, tiles32, cost32);
   return OPF_OK;
+}
+
+// Sets which batch instances are left out of the work lists (r empty: none)
+// and rebuilds the lists and graphs if that changes.
+opf_status set_retired(opf_ctx* c, const std::vector<char>& r) {
+  auto any = [](const std::vector<char>& v) {
+    for (char x : v)
+      if (x) return true;
+    return false;
+  };
+  if (!c->batch || (!any(r) && !any(c->retired)) || r == c->retired) return OPF_OK;
+  c->retired = r;
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  return refresh_geometry(c);
 }
 
 // Resets every instance to the all-zero start (Section 3.4).
@@ -1749,6 +1768,13 @@ opf_status opf_iterate(opf_ctx* c, int32_t n) {
 opf_status opf_solve(opf_ctx* c, opf_resid* out) {
   if (!c) return fail(nullptr, OPF_E_INVALID, "ctx is NULL");
   if (!c->loaded) return fail(c, OPF_E_STATE, not_loaded_msg(c));
+  // Stopped batch instances leave the work lists at block boundaries, so
+  // later blocks launch work only for those still running (their iterates
+  // are untouched either way); the lists are whole again on return.
+  struct Unretire {
+    opf_ctx* c;
+    ~Unretire() { (void)set_retired(c, {}); }
+  } unretire{c};
   const int blk = c->opt.block_iters;
   const int ae = c->opt.adapt_every;
   // graphs need a capturable (non-null) stream and blocks aligned to the
@@ -1765,6 +1791,12 @@ opf_status opf_solve(opf_ctx* c, opf_resid* out) {
     if (s != OPF_OK) return s;
     for (size_t i = 0; i < c->inst.size(); ++i) numeric = numeric || c->h_ctl[i].numeric_bad;
     if (numeric) break;
+    if (c->batch) {
+      std::vector<char> r(c->inst.size());
+      for (size_t i = 0; i < r.size(); ++i) r[i] = c->h_ctl[i].done ? 1 : 0;
+      s = set_retired(c, r);
+      if (s != OPF_OK) return s;
+    }
     // FP64 polish of a single FP32 instance near the tolerance
     if (!c->batch && c->precision == 1 && c->opt.polish_fp64 && c->has64 && !c->h_ctl[0].done) {
       opf_resid r;

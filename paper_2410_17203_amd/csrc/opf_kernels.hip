@@ -1072,9 +1072,17 @@ k_sweep_tile_batch(BatchTab tab) {
         uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(gl)))))));
     if (g < 0) break;
     const int i = find_inst(tab.tile_prefix, tab.n_inst, g);
+    if (descs[i].g.ctl->done) {
+      // a stopped instance: its remaining items in this range are skipped at once
+      if (threadIdx.x == 0) {
+        const int x = (x0 + xs) & 7;
+        const int64_t b = tab.xcd_bounds[x], e = tab.xcd_bounds[x + 1];
+        atomicMax(tab.tile_queue + x, int(min(e, tab.tile_prefix[i + 1]) - b));
+      }
+      continue;
+    }
     const KArgs<R, VT>& a = descs[i];
     Ctl* ctl = a.g.ctl;
-    if (ctl->done) continue;
     const int cur = ctl->cur;
     const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
     const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
