@@ -117,6 +117,15 @@ def test_batched_solve_stops_each_instance_on_its_own(tiles):
     b.iterate(100)
     for i, x in enumerate(res):
         assert b.residuals(i)["iter"] == x["iter"]
+    # the solve left stopped instances out of its work lists as they stopped;
+    # the lists are whole again afterwards: a second solve from zero repeats
+    # the first one bit for bit
+    b.reset()
+    b.solve()
+    for i, x in enumerate(res):
+        y = b.residuals(i)
+        assert (y["iter"], y["converged"], y["objective"], y["rms_primal"], y["rms_dual"]) == \
+            (x["iter"], x["converged"], x["objective"], x["rms_primal"], x["rms_dual"]), i
     # each instance stops where its own single-instance solve stops
     for i, inst in enumerate(insts):
         a = Solver(inst, dtype="f32", eps=1e-3, max_iter=cap, polish_fp64=0, sweep_tiles=tiles)
