@@ -817,6 +817,10 @@ opf_status set_retired(opf_ctx* c, const std::vector<char>& r) {
 opf_status reset_state(opf_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+  // (every launch of the batched tiled sweep is followed by the finalize
+  // that zeroes its work counters; zeroed here too, outside any graph)
+  if (c->batch && c->d_queue)
+    HIP_TRY(c, hipMemsetAsync(c->d_queue, 0, sizeof(int32_t) * 8, c->stream));
   for (size_t i = 0; i < c->inst.size(); ++i) {
     Inst& s = c->inst[i];
     if (s.state_end > s.state_begin)
