@@ -209,7 +209,10 @@ opf_status opf_iterate(opf_ctx* ctx, int32_t n_iters);
 
 /* Iterates until eq. converge holds (for every instance) or max_iter;
  * synchronises.  Returns OPF_OK or OPF_NOT_CONVERGED and instance 0's last
- * residual record in *out. */
+ * residual record in *out.  In a batch, each instance stops on its own; at
+ * each block of block_iters iterations the stopped instances leave the work
+ * lists (their iterates stay as they stopped), which are whole again when
+ * opf_solve returns. */
 opf_status opf_solve(opf_ctx* ctx, opf_resid* out);
 
 /* Synchronises the stream and returns the last residual record (of
@@ -365,8 +368,12 @@ opf_status opf_set_state(opf_ctx* ctx, const void* src, size_t bytes);
  * iterate with FP32 or FP64 duals (not BF16), inner_iters <= 32. */
 
 /* Bytes of device memory the tape of an n_iters run needs, for the loaded
- * network and the active precision: (ceil(n/C) + 1 + C) iterate snapshots,
- * the penalty history and the adjoint arrays. */
+ * network and the active precision: ceil(n/C) checkpoints, C - 1 segment
+ * snapshots and the final iterate (iterate snapshots), the penalty history,
+ * the clip masks of every time-coupled prox of every iteration (two 32-bit
+ * words per bound, lane and slot of each ramp generator and battery), and
+ * the adjoint arrays.  C = 1 keeps every iterate: the adjoint then recomputes
+ * nothing. */
 opf_status opf_tape_workspace_size(opf_ctx* ctx, int32_t n_iters, int32_t checkpoint_every,
                                    size_t* bytes);
 
