@@ -185,6 +185,43 @@ def batched_time_to_tolerance(max_iter):
             "one_at_a_time_iters_total": int(sum(iters_s))}
 
 
+def medium_leg(steps=1000, warmup=50):
+    """The Medium workload (500 nodes, 700 lines, T = 24, K = 50): FP32 and
+    FP64 iterations/s with the sweep's bytes over its time (its state, about
+    22 MB in FP32, stays in the 256 MB last-level cache, so that fraction is
+    cache-resident, not HBM), and time to 1e-3 (FP32 + FP64 polish, and FP64
+    throughout)."""
+    import torch
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.binding import Solver
+    inst = synth.config("medium")
+    out = {"workload": "medium: N=500 L=700 G=100 D=400 B=20 T=24 K=50 (synthetic, seed 500)"}
+    never = dict(eps=0.0, min_iter=2**31 - 1, max_iter=2**31 - 1, polish_fp64=0)
+    for dt in ("f32", "f64"):
+        s = Solver(inst, dtype=dt, **never)
+        el, kt = time_iterations(s, steps, warmup)
+        sw = kt["sweep"]["ms"] / max(kt["sweep"]["launches"], 1)
+        S = 4 if dt == "f32" else 8
+        sweep_bytes = S * (inst.K + 1) * inst.T * (13 * inst.L + 6 * inst.N)
+        out[dt] = {"iters_per_s": steps / el, "sweep_ms": sw,
+                   "sweep_GBps_contracted_cache_resident": sweep_bytes / (sw * 1e-3) / 1e9}
+        s.close()
+        s = Solver(inst, dtype=dt, eps=1e-3, max_iter=20000)
+        s.solve()  # warm-up: builds the graphs
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        out[dt].update({"time_to_tol_s": time.perf_counter() - t0, "time_to_tol_iters": r["iter"],
+                        "time_to_tol_converged": r["status"] == "OPF_OK",
+                        "objective": r["objective"]})
+        s.close()
+    out["f32_objective_rel_err_vs_fp64"] = (abs(out["f32"]["objective"] - out["f64"]["objective"])
+                                            / abs(out["f64"]["objective"]))
+    return out
+
+
 def general_model_rate(inst, steps, warmup):
     """Iterations/s of the FP32 iterate on the same workload extended to the
     general line model: 3 HVDC links (the paper's network has 3 among about
@@ -432,6 +469,9 @@ def main():
     ap.add_argument("--batched-ttt", type=int, default=1,
                     help="1: also time the 64-instance batch to 1e-3 against one-at-a-time solves")
     ap.add_argument("--batched-ttt-max-iter", type=int, default=20000)
+    ap.add_argument("--medium", type=int, default=1,
+                    help="1: also time the Medium workload (FP32 and FP64, iterations/s and "
+                         "time to tolerance)")
     ap.add_argument("--general", type=int, default=1,
                     help="1: also time the general line model (DC links, per-contingency changes)")
     ap.add_argument("--adjoint", type=int, default=1,
@@ -606,6 +646,14 @@ def main():
         b = extra["batched_time_to_tol"]
         log(f"[bench] batch to 1e-3: {b['batched_s']:.2f}s vs {b['one_at_a_time_s']:.2f}s one at a "
             f"time; converged {b['batched_converged']}/{b['instances']}")
+
+    if args.medium:
+        extra["medium"] = medium_leg()
+        m = extra["medium"]
+        log(f"[bench] medium: fp32 {m['f32']['iters_per_s']:.0f} it/s, fp64 {m['f64']['iters_per_s']:.0f} "
+            f"it/s; to 1e-3 fp32+polish {m['f32']['time_to_tol_iters']} it in "
+            f"{m['f32']['time_to_tol_s']:.3f}s, fp64 {m['f64']['time_to_tol_iters']} it in "
+            f"{m['f64']['time_to_tol_s']:.3f}s")
 
     if args.general:
         extra["general_line_model"] = general_model_rate(inst, 100, 10)
