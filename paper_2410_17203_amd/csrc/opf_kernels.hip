@@ -949,6 +949,28 @@ __global__ void __launch_bounds__(kBlock) k_rescale(KArgs<R, VT> a) {
 // block (penalties, counters, convergence) and buffers; finished instances
 // are skipped.  Residual partials are written per (row group, wave) and per
 // device, so no block-wide barrier is needed inside the work loops.
+//
+// The instances' descriptors are read through the constant address space
+// (the host writes them; no kernel does).  Pointers loaded from constant
+// memory are taken by the compiler to address global memory, so each
+// instance's state is accessed with global loads and stores as in the
+// single-instance kernels, whose arguments are constant too.  Read through a
+// generic pointer they would be flat accesses, which also count against the
+// LDS wait counter: every LDS barrier of the tiled sweep would then wait for
+// all of the workgroup's HBM loads in flight.
+template <typename R, typename VT>
+struct BatchDescs {
+  using CA = __attribute__((address_space(4))) const KArgs<R, VT>;
+  const CA* p;
+  __device__ explicit BatchDescs(const void* d) : p((const CA*)d) {}
+  // a copy of instance i's descriptor (its fields live in scalar registers)
+  __device__ KArgs<R, VT> operator[](int i) const { return *(const KArgs<R, VT>*)(p + i); }
+  // buffer k of instance i (k need not be known at compile time)
+  __device__ Buf<R, VT> buf(int i, int k) const {
+    return *(const Buf<R, VT>*)(&p[i].st.buf[k]);
+  }
+  __device__ Ctl* ctl(int i) const { return p[i].g.ctl; }
+};
 
 __device__ inline int find_inst(const int64_t* prefix, int n, int64_t g) {
   int lo = 0, hi = n;
@@ -964,12 +986,12 @@ __device__ inline int find_inst(const int64_t* prefix, int n, int64_t g) {
 
 template <typename R, typename VT, int E>
 __global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
-  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const BatchDescs<R, VT> descs(tab.descs);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t gw = int64_t(blockIdx.x) * (kBlock / kWave) + w;
   if (gw >= tab.total_dev) return;
   const int i = find_inst(tab.dev_prefix, tab.n_inst, gw);
-  const KArgs<R, VT>& a = descs[i];
+  const KArgs<R, VT> a = descs[i];
   Ctl* ctl = a.g.ctl;
   if (ctl->done) return;
   const int j = int(gw - tab.dev_prefix[i]);
@@ -986,17 +1008,17 @@ __global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
 
 template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
-  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const BatchDescs<R, VT> descs(tab.descs);
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
     const int i = find_inst(tab.grp_prefix, tab.n_inst, gi);
-    const KArgs<R, VT>& a = descs[i];
+    const KArgs<R, VT> a = descs[i];
     Ctl* ctl = a.g.ctl;
     if (ctl->done) continue;
     const int cur = ctl->cur;
-    const Buf<R, VT> A = a.st.buf[cur];
-    const Buf<R, VT> B = a.st.buf[cur ^ 1];
+    const Buf<R, VT> A = descs.buf(i, cur);
+    const Buf<R, VT> B = descs.buf(i, cur ^ 1);
     const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
     const bool check = ((ctl->iter + 1) % ctl->check_every) == 0;
     const int64_t li = gi - tab.grp_prefix[i];
@@ -1045,7 +1067,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
 template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_tile_batch(BatchTab tab) {
-  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const BatchDescs<R, VT> descs(tab.descs);
   __shared__ int64_t sItem[2];  // the next item, double-buffered by parity
   const int x0 = blockIdx.x & 7;
   int xs = 0;  // (thread 0) ranges used up so far, own range first
@@ -1072,7 +1094,7 @@ k_sweep_tile_batch(BatchTab tab) {
         uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(gl)))))));
     if (g < 0) break;
     const int i = find_inst(tab.tile_prefix, tab.n_inst, g);
-    if (descs[i].g.ctl->done) {
+    if (descs.ctl(i)->done) {
       // a stopped instance: its remaining items in this range are skipped at once
       if (threadIdx.x == 0) {
         const int x = (x0 + xs) & 7;
@@ -1081,7 +1103,7 @@ k_sweep_tile_batch(BatchTab tab) {
       }
       continue;
     }
-    const KArgs<R, VT>& a = descs[i];
+    const KArgs<R, VT> a = descs[i];
     Ctl* ctl = a.g.ctl;
     const int cur = ctl->cur;
     const R rp = R(ctl->rho_p), rt = R(ctl->rho_th), sv = R(ctl->sv);
@@ -1089,7 +1111,7 @@ k_sweep_tile_batch(BatchTab tab) {
     const int64_t li = g - tab.tile_prefix[i];
     const int r = int(li / a.tp.Q), cq = int(li - int64_t(r) * a.tp.Q);
     const int t0 = r * a.g.tile_run;
-    tile_run<R, VT, GEN>(a, a.st.buf[cur], a.st.buf[cur ^ 1], cq, t0,
+    tile_run<R, VT, GEN>(a, descs.buf(i, cur), descs.buf(i, cur ^ 1), cq, t0,
                          min(a.tp.T, t0 + a.g.tile_run), rp, rt, sv, check, acc,
                          check ? a.g.part_sweep + 5 * li : nullptr);
   }
@@ -1097,8 +1119,7 @@ k_sweep_tile_batch(BatchTab tab) {
 
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
-  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
-  const KArgs<R, VT>& a = descs[blockIdx.x];
+  const KArgs<R, VT> a = BatchDescs<R, VT>(tab.descs)[blockIdx.x];
   // the tiled sweep's work counters start the next launch at zero
   if (blockIdx.x == 0 && threadIdx.x < 8) tab.tile_queue[threadIdx.x] = 0;
   const int64_t ng = tab.grp_prefix[blockIdx.x + 1] - tab.grp_prefix[blockIdx.x];
@@ -1110,12 +1131,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
 
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_rescale_batch(BatchTab tab) {
-  const KArgs<R, VT>* descs = reinterpret_cast<const KArgs<R, VT>*>(tab.descs);
+  const BatchDescs<R, VT> descs(tab.descs);
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
     const int i = find_inst(tab.grp_prefix, tab.n_inst, gi);
-    const KArgs<R, VT>& a = descs[i];
+    const KArgs<R, VT> a = descs[i];
     Ctl* ctl = a.g.ctl;
     if (ctl->scale_iter != ctl->launches) continue;
     const R su = R(ctl->su);
@@ -1123,8 +1144,8 @@ __global__ void __launch_bounds__(kBlock) k_rescale_batch(BatchTab tab) {
     const int lpr = a.g.lanes_per_row;
     const int rw = lane / lpr, q = lane - rw * lpr;
     const int64_t li = gi - tab.grp_prefix[i];
-    rescale_row(a, a.st.buf[ctl->cur], su, (li * (kBlock / kWave) + w) * (kWave / lpr) + rw, q,
-                lpr);
+    rescale_row(a, descs.buf(i, ctl->cur), su, (li * (kBlock / kWave) + w) * (kWave / lpr) + rw,
+                q, lpr);
   }
 }
 
