@@ -517,7 +517,7 @@ void plan_batch(int count, Layout& L, BatchPlan& b) {
   b.grp32 = L.take(sizeof(int64_t) * (count + 1));
   b.tiles64 = L.take(sizeof(int64_t) * (count + 1));
   b.tiles32 = L.take(sizeof(int64_t) * (count + 1));
-  b.queue = L.take(sizeof(int32_t) * 8);
+  b.queue = L.take(sizeof(int32_t) * 9);  // work counters [8], rescale flag
 }
 
 template <typename R, typename VT>
@@ -769,6 +769,7 @@ opf_status refresh_geometry(opf_ctx* c) {
     t.tile_prefix = d_tiles;
     t.total_tiles = tiles[n];
     t.tile_queue = c->d_queue;
+    t.rescale_flag = c->d_queue + 8;
     {
       double total = 0.0;
       for (int i = 0; i < n; ++i) total += cost[i] * double(tiles[i + 1] - tiles[i]);
@@ -818,9 +819,10 @@ opf_status reset_state(opf_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
   // (every launch of the batched tiled sweep is followed by the finalize
-  // that zeroes its work counters; zeroed here too, outside any graph)
+  // that zeroes its work counters; zeroed here too, with the rescale flag,
+  // outside any graph)
   if (c->batch && c->d_queue)
-    HIP_TRY(c, hipMemsetAsync(c->d_queue, 0, sizeof(int32_t) * 8, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_queue, 0, sizeof(int32_t) * 9, c->stream));
   for (size_t i = 0; i < c->inst.size(); ++i) {
     Inst& s = c->inst[i];
     if (s.state_end > s.state_begin)

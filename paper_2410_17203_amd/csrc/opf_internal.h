@@ -236,6 +236,8 @@ struct BatchTab {
   int64_t xcd_bounds[9];      // the work list split into 8 XCD ranges of equal estimated work
   int32_t* tile_queue;        // [8] items taken from each XCD range in this launch (zeroed
                               // by k_finalize_batch after every launch)
+  int32_t* rescale_flag;      // set by k_finalize_batch when some instance's penalties
+                              // changed, read by k_rescale_batch, cleared by the next sweep
   int64_t total_dev;
   int64_t total_grps;
 };

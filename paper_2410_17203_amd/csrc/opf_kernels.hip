@@ -1009,6 +1009,7 @@ __global__ void __launch_bounds__(kBlock) k_devices_batch(BatchTab tab) {
 template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchTab tab) {
   const BatchDescs<R, VT> descs(tab.descs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tab.rescale_flag = 0;  // (set by the finalize after)
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
@@ -1068,6 +1069,7 @@ template <typename R, typename VT, bool GEN>
 __global__ void __launch_bounds__(kTileBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_sweep_tile_batch(BatchTab tab) {
   const BatchDescs<R, VT> descs(tab.descs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tab.rescale_flag = 0;  // (set by the finalize after)
   __shared__ int64_t sItem[2];  // the next item, double-buffered by parity
   const int x0 = blockIdx.x & 7;
   int xs = 0;  // (thread 0) ranges used up so far, own range first
@@ -1127,25 +1129,37 @@ __global__ void __launch_bounds__(kBlock) k_finalize_batch(BatchTab tab) {
   const int64_t n_items = tab.tile_prefix[blockIdx.x + 1] - tab.tile_prefix[blockIdx.x];
   const int n_sweep = tab.tile_blocks > 0 ? int(n_items) : int(ng * (kBlock / kWave));
   finalize_body(a, n_sweep, a.tp.Jnc);
+  // (thread 0 has just set the control block: a penalty change to apply)
+  if (threadIdx.x == 0 && a.g.ctl->scale_iter == a.g.ctl->launches && a.g.ctl->su != 1.0)
+    *tab.rescale_flag = 1;
 }
 
 template <typename R, typename VT>
 __global__ void __launch_bounds__(kBlock) k_rescale_batch(BatchTab tab) {
+  if (*tab.rescale_flag == 0) return;  // no instance changed its penalties
   const BatchDescs<R, VT> descs(tab.descs);
   const Sweep sweep = xcd_sweep(blockIdx.x, gridDim.x, tab.total_grps);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  for (int64_t gi = sweep.first; gi < sweep.end; gi += sweep.step) {
+  // (the block's row groups ascend, so each instance is looked up once, and
+  // an instance without a penalty change is passed over in one step)
+  for (int64_t gi = sweep.first; gi < sweep.end;) {
     const int i = find_inst(tab.grp_prefix, tab.n_inst, gi);
+    const int64_t gend = min(tab.grp_prefix[i + 1], sweep.end);
     const KArgs<R, VT> a = descs[i];
     Ctl* ctl = a.g.ctl;
-    if (ctl->scale_iter != ctl->launches) continue;
     const R su = R(ctl->su);
-    if (su == R(1)) continue;
-    const int lpr = a.g.lanes_per_row;
-    const int rw = lane / lpr, q = lane - rw * lpr;
-    const int64_t li = gi - tab.grp_prefix[i];
-    rescale_row(a, descs.buf(i, ctl->cur), su, (li * (kBlock / kWave) + w) * (kWave / lpr) + rw,
-                q, lpr);
+    const bool act = ctl->scale_iter == ctl->launches && su != R(1);
+    if (act) {
+      const int lpr = a.g.lanes_per_row;
+      const int rw = lane / lpr, q = lane - rw * lpr;
+      const Buf<R, VT> C = descs.buf(i, ctl->cur);
+      for (; gi < gend; gi += sweep.step) {
+        const int64_t li = gi - tab.grp_prefix[i];
+        rescale_row(a, C, su, (li * (kBlock / kWave) + w) * (kWave / lpr) + rw, q, lpr);
+      }
+    } else {
+      gi += (gend - gi + sweep.step - 1) / sweep.step * sweep.step;  // first one >= gend
+    }
   }
 }
 
