@@ -162,9 +162,25 @@ opf_status opf_workspace_size(opf_ctx* ctx, const opf_network* net, size_t* byte
 /* Validates and copies the network into the workspace (d_workspace: device
  * pointer, 256-byte aligned, at least opf_workspace_size bytes) and resets
  * the iterate to the all-zero start of Section 3.4.  Synchronises the
- * stream.  Invalid data returns OPF_E_INVALID and leaves ctx unchanged. */
+ * stream.  Invalid data returns OPF_E_INVALID and leaves ctx unchanged.
+ * Before anything is changed, the tables derived from the network (see
+ * opf_check_network) are bounds-checked on the host. */
 opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
                             void* d_workspace, size_t bytes);
+
+/* Host-only check of a network, with no device and no context: the data
+ * checks of opf_load_network under opt (NULL: opf_default_options), then
+ * every index of the tables the kernels read through, against the range
+ * each kernel assumes: the node CSR over line terminals (Section 2.2's
+ * incidence: each terminal's line, end and far node) and over devices, the
+ * node clusters of the tiled sweep with their line tables and per-terminal
+ * line slots, and the ramp generator, DC link and per-contingency change
+ * indices.  opf_load_network and opf_load_batch run the same check.
+ * tiled (may be NULL) receives 1 when the clusters of the tiled sweep exist
+ * (no node has more lines or devices than a cluster holds), else 0.
+ * Returns OPF_OK or OPF_E_INVALID, the reason in opf_last_error(NULL) (kept
+ * per thread). */
+opf_status opf_check_network(const opf_network* net, const opf_options* opt, int32_t* tiled);
 
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight serving loops, harnesses that forbid allocation): as

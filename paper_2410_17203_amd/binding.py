@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "opf_default_options": (None, [POINTER(Options)]),
         "opf_create": (c_int32, [POINTER(Options), POINTER(c_void_p)]),
+        "opf_check_network": (c_int32, [POINTER(Network), POINTER(Options), POINTER(c_int32)]),
         "opf_workspace_size": (c_int32, [P, POINTER(Network), POINTER(c_size_t)]),
         "opf_load_network": (c_int32, [P, POINTER(Network), c_void_p, c_size_t]),
         "opf_load_network_static": (c_int32, [P, POINTER(Network)]),
@@ -225,6 +226,20 @@ def _options(dtype: str, dual_dtype: Optional[str], stream_ptr: int, **kw) -> Op
         setattr(o, k, float(v) if isinstance(getattr(o, k), float) else int(v))
     o.hip_stream = c_void_p(stream_ptr)
     return o
+
+
+def check_network(inst, dtype: str = "f64", dual_dtype: Optional[str] = None, **opts) -> bool:
+    """Host-only check of one network (opf_check_network): raises OpfError
+    with the library's reason if it would be rejected, else returns whether
+    the tiled sweep's clusters exist.  Needs no GPU."""
+    lib = load_library()
+    arrays = NetworkArrays(inst)
+    o = _options(dtype, dual_dtype, 0, **opts)
+    tiled = c_int32(-1)
+    st = lib.opf_check_network(byref(arrays.net), byref(o), byref(tiled))
+    if st != 0:
+        raise OpfError(f"{st}: {lib.opf_last_error(None).decode()}")
+    return bool(tiled.value)
 
 
 class Solver:

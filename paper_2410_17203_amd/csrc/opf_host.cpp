@@ -851,40 +851,19 @@ opf_status reset_state(opf_ctx* c) {
 }
 
 // Validates all networks and lays out the workspace.
-opf_status plan_all(opf_ctx* c, const opf_network* nets, int count, std::vector<Inst>& insts,
-                    std::vector<InstPlan>& plans, BatchPlan& bp, Layout& lay) {
-  if (count < 1) return fail(c, OPF_E_INVALID, "need at least one network");
-  if (!nets) return fail(c, OPF_E_INVALID, "networks are NULL");
-  insts.assign(count, Inst());
-  plans.assign(count, InstPlan());
-  for (int i = 0; i < count; ++i) {
-    opf_status s = validate(c, &nets[i]);
-    if (s != OPF_OK) {
-      if (count > 1) c->err = "instance " + std::to_string(i) + ": " + c->err;
-      return s;
-    }
-    set_sizes(insts[i], &nets[i]);
-  }
-  if (count > 1) plan_batch(count, lay, bp);
-  for (int i = 0; i < count; ++i) plan_instance(c, insts[i], lay, plans[i]);
-  return OPF_OK;
-}
+// The derived host tables of one network: node CSR over line terminals and
+// devices, the tiled sweep's clusters, DC link and change lists.
+struct Tables {
+  std::vector<int32_t> outage_k, lptr, nptr, lterm, nterm, nc_node, clus_n0, tl_ptr, tl, tcsr,
+      ramp_idx, line_dc, chg_ptr;
+  std::vector<double> deg, sus;
+  std::vector<LineChg> chg;
+  bool tiles_ok = false;
+  int Q = 0;  // clusters (0: the tiled sweep is not available)
+  double load_rms = 1.0;
+};
 
-opf_status workspace_size(opf_ctx* c, const opf_network* nets, int count, size_t* bytes) {
-  if (!c || !bytes) return fail(c, OPF_E_INVALID, "NULL argument");
-  std::vector<Inst> insts;
-  std::vector<InstPlan> plans;
-  BatchPlan bp{};
-  Layout lay;
-  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay);
-  if (s != OPF_OK) return s;
-  *bytes = lay.total;
-  return OPF_OK;
-}
-
-// Builds the derived host data of one network and copies it to the device.
-opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const InstPlan& p) {
-  char* ws = c->ws;
+void build_tables(const opf_network* n, const Inst& s, Tables& t) {
   const int N = s.N, T = s.T, L = s.L, G = s.G, D = s.D, B = s.B, Jnc = s.Jnc, Kpp = s.Kpp;
   std::vector<int32_t> outage_k(Kpp, -1);
   for (int k = 1; k <= s.K; ++k) outage_k[k] = n->outage[k - 1];
@@ -974,7 +953,6 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
       tl_ptr.push_back(int(tl.size() / 4));
     }
   }
-  s.topo.Q = tiles_ok ? int(clus_n0.size()) - 1 : 0;
   std::vector<int32_t> ramp_idx(G, -1);
   {
     int r = 0;
@@ -1021,6 +999,194 @@ opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const Inst
   for (size_t i = 0; i < size_t(D) * T; ++i) lsum += n->load_d[i] * n->load_d[i];
   const double load_rms = (size_t(D) * T > 0) ? std::sqrt(lsum / double(size_t(D) * T)) : 1.0;
 
+  t.outage_k = std::move(outage_k);
+  t.lptr = std::move(lptr);
+  t.nptr = std::move(nptr);
+  t.lterm = std::move(lterm);
+  t.nterm = std::move(nterm);
+  t.nc_node = std::move(nc_node);
+  t.deg = std::move(deg);
+  t.tiles_ok = tiles_ok;
+  t.Q = tiles_ok ? int(clus_n0.size()) - 1 : 0;
+  t.clus_n0 = std::move(clus_n0);
+  t.tl_ptr = std::move(tl_ptr);
+  t.tl = std::move(tl);
+  t.tcsr = std::move(tcsr);
+  t.ramp_idx = std::move(ramp_idx);
+  t.line_dc = std::move(line_dc);
+  t.sus = std::move(sus);
+  t.chg_ptr = std::move(chg_ptr);
+  t.chg = std::move(chg);
+  t.load_rms = load_rms;
+}
+
+// Checks every index of the derived tables that a kernel reads through
+// against the range the kernel assumes (host-side bounds check of the
+// device tables: node CSR, clusters and their line tables, device, DC link
+// and change indices).  Returns an empty string, or what failed.
+std::string check_tables(const opf_network* n, const Inst& s, const Tables& t) {
+  const int N = s.N, L = s.L, G = s.G, Jnc = s.Jnc, Kpp = s.Kpp;
+  auto in = [](int64_t x, int64_t lo, int64_t hi) { return x >= lo && x < hi; };
+  auto at = [](const char* what, int64_t i) { return std::string(what) + " at " + std::to_string(i); };
+  if (int(t.outage_k.size()) != Kpp) return "outage table size";
+  for (int k = 0; k < Kpp; ++k) {
+    const int o = t.outage_k[k];
+    // (-1 for the base case, the padding, and a contingency that removes no line)
+    if (k >= 1 && k <= s.K ? !in(o, -1, L) : o != -1) return at("outage index", k);
+  }
+  // node CSR over line terminals: entry 2 l + end at the node of that end,
+  // with the node at the line's other end
+  auto csr_ok = [&](const std::vector<int32_t>& ptr, int64_t total) {
+    if (int(ptr.size()) != N + 1 || ptr[0] != 0 || ptr[N] != total) return false;
+    for (int v = 0; v < N; ++v)
+      if (ptr[v + 1] < ptr[v]) return false;
+    return true;
+  };
+  if (!csr_ok(t.lptr, 2 * int64_t(L))) return "line terminal CSR pointers";
+  for (int v = 0; v < N; ++v)
+    for (int q = t.lptr[v]; q < t.lptr[v + 1]; ++q) {
+      const int e = t.lterm[2 * size_t(q)], far = t.lterm[2 * size_t(q) + 1];
+      if (!in(e, 0, 2 * int64_t(L))) return at("line terminal entry", q);
+      const int l = e >> 1;
+      const bool to_end = e & 1;
+      if ((to_end ? n->line_to[l] : n->line_from[l]) != v ||
+          (to_end ? n->line_from[l] : n->line_to[l]) != far)
+        return at("line terminal ends", q);
+    }
+  if (!csr_ok(t.nptr, Jnc)) return "device CSR pointers";
+  if (int(t.nc_node.size()) != Jnc) return "device node table size";
+  for (int j = 0; j < Jnc; ++j)
+    if (!in(t.nc_node[j], 0, N)) return at("device node", j);
+  for (int v = 0; v < N; ++v)
+    for (int q = t.nptr[v]; q < t.nptr[v + 1]; ++q)
+      if (!in(t.nterm[q], 0, Jnc) || t.nc_node[t.nterm[q]] != v) return at("device entry", q);
+  for (int v = 0; v < N; ++v)
+    if (!(t.deg[v] >= 1.0)) return at("node degree", v);
+  // clusters of the tiled sweep: consecutive nodes, their lines, and for
+  // every line terminal its line's index in the cluster's table
+  if (t.tiles_ok) {
+    const int Q = t.Q;
+    if (Q < 1 || int(t.clus_n0.size()) != Q + 1 || int(t.tl_ptr.size()) != Q + 1)
+      return "cluster table sizes";
+    if (t.clus_n0[0] != 0 || t.clus_n0[Q] != N || t.tl_ptr[0] != 0 ||
+        size_t(t.tl_ptr[Q]) * 4 != t.tl.size())
+      return "cluster table ends";
+    for (int cq = 0; cq < Q; ++cq) {
+      const int n0 = t.clus_n0[cq], n1 = t.clus_n0[cq + 1];
+      const int j0 = t.tl_ptr[cq], j1 = t.tl_ptr[cq + 1];
+      if (!(n1 > n0 && n1 - n0 <= kTileNodes)) return at("cluster nodes", cq);
+      if (!(j1 >= j0 && j1 - j0 <= kTileLines)) return at("cluster lines", cq);
+      if (t.lptr[n1] - t.lptr[n0] > 2 * kTileLines) return at("cluster terminals", cq);
+      if (t.nptr[n1] - t.nptr[n0] > kTileDev) return at("cluster devices", cq);
+      for (int j = j0; j < j1; ++j) {
+        const int32_t* e = &t.tl[4 * size_t(j)];
+        if (!in(e[0], 0, L)) return at("cluster line", j);
+        const int f = n->line_from[e[0]], h = n->line_to[e[0]];
+        const bool fin = f >= n0 && f < n1, hin = h >= n0 && h < n1;
+        if (e[1] != (fin ? f - n0 : -1) || e[2] != (hin ? h - n0 : -1)) return at("cluster line ends", j);
+        if (e[3] != (fin && hin ? -1 : (fin ? h : f)) || !in(e[3], -1, N) || (!fin && !hin))
+          return at("cluster far node", j);
+      }
+      for (int q = t.lptr[n0]; q < t.lptr[n1]; ++q) {
+        const int x = t.tcsr[q];
+        if (!in(x >> 1, 0, j1 - j0) || t.tl[4 * size_t(j0 + (x >> 1))] != (t.lterm[2 * size_t(q)] >> 1) ||
+            (x & 1) != (t.lterm[2 * size_t(q)] & 1))
+          return at("cluster terminal", q);
+      }
+    }
+  }
+  int nr = 0;
+  for (int g = 0; g < G; ++g) {
+    if (t.ramp_idx[g] >= 0 && t.ramp_idx[g] != nr++) return at("ramp index", g);
+    if (t.ramp_idx[g] < -1) return at("ramp index", g);
+  }
+  if (nr != s.nR) return "ramp generator count";
+  int nd = 0;
+  for (int l = 0; l < L; ++l) {
+    if (t.line_dc[l] >= 0 && t.line_dc[l] != nd++) return at("DC link index", l);
+    if (t.line_dc[l] < -1) return at("DC link index", l);
+  }
+  if (nd != s.Ldc) return "DC link count";
+  if (int(t.chg_ptr.size()) != L + 1 || t.chg_ptr[0] != 0 || t.chg_ptr[L] != s.n_chg)
+    return "change CSR pointers";
+  for (int l = 0; l < L; ++l) {
+    if (t.chg_ptr[l + 1] < t.chg_ptr[l]) return at("change CSR pointers", l);
+    for (int q = t.chg_ptr[l]; q < t.chg_ptr[l + 1]; ++q) {
+      const LineChg& ch = t.chg[q];
+      if (!in(ch.k, 1, s.K + 1) || !in(ch.z, -1, s.Zc)) return at("change entry", q);
+      if (q > t.chg_ptr[l] && !(t.chg[q - 1].k < ch.k)) return at("change order", q);
+    }
+  }
+  return std::string();
+}
+
+// Validates the networks and sizes their workspace; with tabs, also builds
+// and bounds-checks their derived tables (before anything is changed).
+opf_status plan_all(opf_ctx* c, const opf_network* nets, int count, std::vector<Inst>& insts,
+                    std::vector<InstPlan>& plans, BatchPlan& bp, Layout& lay,
+                    std::vector<Tables>* tabs = nullptr) {
+  if (count < 1) return fail(c, OPF_E_INVALID, "need at least one network");
+  if (!nets) return fail(c, OPF_E_INVALID, "networks are NULL");
+  insts.assign(count, Inst());
+  plans.assign(count, InstPlan());
+  if (tabs) tabs->assign(count, Tables());
+  for (int i = 0; i < count; ++i) {
+    opf_status s = validate(c, &nets[i]);
+    if (s != OPF_OK) {
+      if (count > 1) c->err = "instance " + std::to_string(i) + ": " + c->err;
+      return s;
+    }
+    set_sizes(insts[i], &nets[i]);
+    if (tabs) {
+      build_tables(&nets[i], insts[i], (*tabs)[i]);
+      const std::string why = check_tables(&nets[i], insts[i], (*tabs)[i]);
+      if (!why.empty())
+        return fail(c, OPF_E_INVALID,
+                    (count > 1 ? "instance " + std::to_string(i) + ": " : std::string()) +
+                        "derived table check failed: " + why);
+    }
+  }
+  if (count > 1) plan_batch(count, lay, bp);
+  for (int i = 0; i < count; ++i) plan_instance(c, insts[i], lay, plans[i]);
+  return OPF_OK;
+}
+
+opf_status workspace_size(opf_ctx* c, const opf_network* nets, int count, size_t* bytes) {
+  if (!c || !bytes) return fail(c, OPF_E_INVALID, "NULL argument");
+  std::vector<Inst> insts;
+  std::vector<InstPlan> plans;
+  BatchPlan bp{};
+  Layout lay;
+  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay);
+  if (s != OPF_OK) return s;
+  *bytes = lay.total;
+  return OPF_OK;
+}
+
+// Copies one network's data and derived tables to the device.
+opf_status upload_instance(opf_ctx* c, const opf_network* n, Inst& s, const InstPlan& p,
+                           const Tables& t) {
+  char* ws = c->ws;
+  const int N = s.N, T = s.T, L = s.L, G = s.G, D = s.D, B = s.B, Jnc = s.Jnc, Kpp = s.Kpp;
+  const auto& outage_k = t.outage_k;
+  const auto& lptr = t.lptr;
+  const auto& nptr = t.nptr;
+  const auto& lterm = t.lterm;
+  const auto& nterm = t.nterm;
+  const auto& nc_node = t.nc_node;
+  const auto& deg = t.deg;
+  const auto& clus_n0 = t.clus_n0;
+  const auto& tl_ptr = t.tl_ptr;
+  const auto& tl = t.tl;
+  const auto& tcsr = t.tcsr;
+  const auto& ramp_idx = t.ramp_idx;
+  const auto& line_dc = t.line_dc;
+  const auto& sus = t.sus;
+  const auto& chg_ptr = t.chg_ptr;
+  const auto& chg = t.chg;
+  const bool tiles_ok = t.tiles_ok;
+  const double load_rms = t.load_rms;
+  s.topo.Q = t.Q;
   auto up = [&](size_t off, const void* src, size_t nbytes) -> hipError_t {
     if (nbytes == 0) return hipSuccess;
     return hipMemcpyAsync(ws + off, src, nbytes, hipMemcpyHostToDevice, c->stream);
@@ -1140,9 +1306,10 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
     return fail(c, OPF_E_INVALID, "workspace must be 256-byte aligned");
   std::vector<Inst> insts;
   std::vector<InstPlan> plans;
+  std::vector<Tables> tabs;
   BatchPlan bp{};
   Layout lay;
-  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay);
+  opf_status s = plan_all(c, nets, count, insts, plans, bp, lay, &tabs);
   if (s != OPF_OK) return s;
   if (bytes < lay.total)
     return fail(c, OPF_E_OOM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
@@ -1168,7 +1335,7 @@ opf_status load(opf_ctx* c, const opf_network* nets, int count, void* d_ws, size
   HIP_TRY(c, hipMemsetAsync(c->ws, 0, lay.total, c->stream));
   c->max_T = 1;
   for (int i = 0; i < count; ++i) {
-    s = upload_instance(c, &nets[i], insts[i], plans[i]);
+    s = upload_instance(c, &nets[i], insts[i], plans[i], tabs[i]);
     if (s != OPF_OK) return s;
     c->max_T = std::max(c->max_T, insts[i].T);
   }
@@ -1692,6 +1859,26 @@ opf_status opf_create(const opf_options* opt, opf_ctx** out) {
   }
   (void)hipGetLastError();
   *out = c;
+  return OPF_OK;
+}
+
+opf_status opf_check_network(const opf_network* n, const opf_options* opt, int32_t* tiled) {
+  opf_ctx tmp;  // host only: no stream, no device memory
+  if (opt)
+    tmp.opt = *opt;
+  else
+    opf_default_options(&tmp.opt);
+  std::vector<Inst> insts;
+  std::vector<InstPlan> plans;
+  std::vector<Tables> tabs;
+  BatchPlan bp{};
+  Layout lay;
+  const opf_status s = plan_all(&tmp, n, 1, insts, plans, bp, lay, &tabs);
+  if (s != OPF_OK) {
+    g_create_error = tmp.err;
+    return s;
+  }
+  if (tiled) *tiled = tabs[0].tiles_ok ? 1 : 0;
   return OPF_OK;
 }
 
