@@ -171,8 +171,9 @@ opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
 /* Host-only check of a network, with no device and no context: the data
  * checks of opf_load_network under opt (NULL: opf_default_options), then
  * every index of the tables the kernels read through, against the range
- * each kernel assumes: the node CSR over line terminals (Section 2.2's
- * incidence: each terminal's line, end and far node) and over devices, the
+ * each kernel assumes: the node CSR over line terminals (the per-terminal
+ * incidence of Section 4.3: each terminal's line, end and far node) and
+ * over devices, the
  * node clusters of the tiled sweep with their line tables and per-terminal
  * line slots, and the ramp generator, DC link and per-contingency change
  * indices.  opf_load_network and opf_load_batch run the same check.
