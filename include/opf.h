@@ -173,10 +173,9 @@ opf_status opf_load_network(opf_ctx* ctx, const opf_network* net,
  * every index of the tables the kernels read through, against the range
  * each kernel assumes: the node CSR over line terminals (the per-terminal
  * incidence of Section 4.3: each terminal's line, end and far node) and
- * over devices, the
- * node clusters of the tiled sweep with their line tables and per-terminal
- * line slots, and the ramp generator, DC link and per-contingency change
- * indices.  opf_load_network and opf_load_batch run the same check.
+ * over devices, the node clusters of the tiled sweep with their line
+ * tables and per-terminal line slots, and the ramp generator, DC link and
+ * per-contingency change indices.  opf_load_network and opf_load_batch run the same check.
  * tiled (may be NULL) receives 1 when the clusters of the tiled sweep exist
  * (no node has more lines or devices than a cluster holds), else 0.
  * Returns OPF_OK or OPF_E_INVALID, the reason in opf_last_error(NULL) (kept
