@@ -202,9 +202,9 @@ opf_status opf_check_network(const opf_network* net, const opf_options* opt, int
 opf_status opf_load_network_static(opf_ctx* ctx, const opf_network* net);
 
 /* Batched form (several independent instances of uneven size in one context;
- * the paper batches scenarios in Section 5.5): the workspace holds all of
- * them and every phase of an iteration is one launch over a work list
- * spanning all instances.  Each instance keeps its own penalties, counters
+ * the paper solves its planning scenarios as one batch in Section 5.6): the
+ * workspace holds all of them and every phase of an iteration is one launch
+ * over a work list spanning all instances.  Each instance keeps its own penalties, counters
  * and convergence flag; converged instances are skipped.  FP64 polishing is
  * not applied to batches.  Instance indices follow the order of nets. */
 opf_status opf_workspace_size_batch(opf_ctx* ctx, const opf_network* nets, int32_t count,
