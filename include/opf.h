@@ -21,7 +21,11 @@
  *     behind opf_load_network_static, part of the library's image;
  *   - all device work is enqueued on the stream given in opf_options and
  *     is asynchronous unless a function says it synchronises;
- *   - a context is not thread-safe; use one context per stream.
+ *   - a context is not thread-safe; use one context per stream.  Distinct
+ *     contexts may be driven from distinct host threads at once (graph
+ *     capture is thread-local; the only global state is the per-thread
+ *     text of opf_last_error(NULL) and the fixed array's bookkeeping,
+ *     which is locked).
  */
 #ifndef OPF_H
 #define OPF_H
