@@ -103,12 +103,40 @@ def batched_rates(iters, dtype, dual_dtype):
         return dt
 
     t_batch = run(insts)
-    t_single = sum(run(i) for i in insts)
+    # one at a time: every instance in its own context (its configuration
+    # from the autotuner, graphs built), solved one after another, then the
+    # same contexts four at a time, each on its own stream from its own host
+    # thread (the GPU runs four hardware queues per process)
+    singles = []
+    for x in insts:
+        s = Solver(x, **opts)
+        _autotune(s)
+        s.solve()
+        s.reset()
+        singles.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in singles:
+        s.solve()
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    for s in singles:
+        s.reset()
+    torch.cuda.synchronize()
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(4) as ex:
+        list(ex.map(lambda g: [s.solve() for s in g], [singles[w::4] for w in range(4)]))
+    torch.cuda.synchronize()
+    t_four = time.perf_counter() - t0
+    for s in singles:
+        s.close()
     n = len(insts)
     elems = sum((13 * i.L + 2 * (i.G + i.D + i.B) + 6 * i.N) * (i.K + 1) * i.T for i in insts)
     out = {"instances": n, "iters": iters, "state_dtype": dtype, "dual_dtype": dual_dtype,
            "batched_inst_iters_per_s": n * iters / t_batch,
            "one_at_a_time_inst_iters_per_s": n * iters / t_single,
+           "four_streams_inst_iters_per_s": n * iters / t_four,
            "speedup": t_single / t_batch,
            "algorithmic_elements_per_iteration": elems}
     # per-kernel times of the batch (events around each launch, so no graphs)
@@ -639,7 +667,8 @@ def main():
         for b in extra["batched"]:
             log(f"[bench] batch of {b['instances']} ({b['dual_dtype']} duals): "
                 f"{b['batched_inst_iters_per_s']:.0f} vs {b['one_at_a_time_inst_iters_per_s']:.0f} "
-                f"instance-iterations/s one at a time")
+                f"instance-iterations/s one at a time, "
+                f"{b['four_streams_inst_iters_per_s']:.0f} four at a time on their own streams")
 
     if args.batched_ttt:
         extra["batched_time_to_tol"] = batched_time_to_tolerance(args.batched_ttt_max_iter)
