@@ -269,6 +269,38 @@ def general_model_rate(inst, steps, warmup):
     return out
 
 
+def planning_leg(steps, scenarios=8, workers_list=(1, 4)):
+    """Wall-clock of the gradient-based planning loop (Section 5.6 shape:
+    8 load scenarios of the 500-node grid with T = 24, here with K = 20
+    contingencies; each step a warm-started recorded solve of 250..1000
+    iterations and its adjoint per scenario), with the scenarios one after
+    another and several at a time on their own streams."""
+    import numpy as np
+    import torch
+    from paper_2410_17203_amd import synth
+    from paper_2410_17203_amd.planning import plan_capacities
+    sc = []
+    for m in range(scenarios):
+        x = synth.config("medium", K=20)
+        rng = np.random.default_rng(200 + m)
+        x.load_d = np.asarray(x.load_d) * rng.uniform(0.95, 1.05, np.shape(x.load_d))
+        sc.append(x)
+    L, G = len(sc[0].line_from), len(sc[0].gen_node)
+    out = {"workload": f"{scenarios} scenarios of medium with K=20 (500 nodes, T=24), FP32",
+           "steps": steps}
+    for w in workers_list:
+        t0 = time.perf_counter()
+        r = plan_capacities(sc, steps=steps, step_size=1e-4, line_cost=np.full(L, 1.0),
+                            gen_cost=np.full(G, 1.0), min_iters=250, max_iters=1000, eps=1e-3,
+                            dtype="f32", workers=w)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"workers_{w}"] = {"s": dt, "s_per_evaluation": dt / (steps + 1),
+                               "losses": [x.loss for x in r.steps],
+                               "iterations": [x.iterations for x in r.steps]}
+    return out
+
+
 def adjoint_times(n_iters, every, dtype):
     """Wall-clock of the recorded forward run and of the adjoint on the
     differentiation workload (gradient of cost + <w, dispatch> w.r.t. load,
@@ -504,6 +536,8 @@ def main():
                     help="1: also time the general line model (DC links, per-contingency changes)")
     ap.add_argument("--adjoint", type=int, default=1,
                     help="1: also time 1000 unrolled iterations forward + adjoint (diff workload)")
+    ap.add_argument("--planning", type=int, default=0,
+                    help="N > 0: time N steps of the planning loop over 8 scenarios")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-k", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=8)
@@ -683,6 +717,12 @@ def main():
             f"it/s; to 1e-3 fp32+polish {m['f32']['time_to_tol_iters']} it in "
             f"{m['f32']['time_to_tol_s']:.3f}s, fp64 {m['f64']['time_to_tol_iters']} it in "
             f"{m['f64']['time_to_tol_s']:.3f}s")
+
+    if args.planning > 0:
+        extra["planning"] = planning_leg(args.planning)
+        pl = extra["planning"]
+        log(f"[bench] planning, {args.planning} steps: " + ", ".join(
+            f"{k} {v['s']:.2f}s" for k, v in pl.items() if k.startswith("workers_")))
 
     if args.general:
         extra["general_line_model"] = general_model_rate(inst, 100, 10)
