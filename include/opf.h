@@ -114,8 +114,10 @@ void opf_default_options(opf_options* opt);
  * DC link only the capacity applies.  A (contingency, line) pair appears at
  * most once and never repeats that contingency's outage[] line.  n_chg = 0
  * (the arrays may be NULL): the N-1 outages only.
- * The adjoint (opf_tape_forward, opf_adjoint) rejects networks with DC links
- * or changes. */
+ * The adjoint (opf_tape_forward, opf_adjoint) covers DC links and changes:
+ * the derivative with respect to line_cap[l] collects the contingencies in
+ * which line l keeps its own capacity (not those a change rerates or where
+ * it is out). */
 typedef struct {
   int32_t N, T, K;
   int32_t L;

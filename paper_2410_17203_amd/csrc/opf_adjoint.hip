@@ -86,7 +86,14 @@ __device__ inline void node_adj(const AdjArgs<R>& a, size_t off, int n, R mw, R 
 }
 
 // Reverse of one (period, node) row and one 16-byte vector of contingencies.
-template <typename R>
+// GEN: the general line model (Section 2.3: DC links, per-contingency line
+// parameters), whose special lines the forward took through line_prox_gen:
+// per contingency a line is then an AC line with that contingency's
+// susceptance and capacity (mode 0), out of service with its held half
+// phase difference as state (mode 1: the N-1 outage, state Td, or a change
+// that takes it out, state Tz), or a DC link (mode 2: flow at the clipped
+// midpoint, half difference as state Hd).
+template <typename R, bool GEN>
 __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int q1, R mw, R mt,
                                R& gsp, R& gsb) {
   constexpr int VEC = 16 / sizeof(R);
@@ -122,9 +129,26 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
     const VR Bx = *reinterpret_cast<const VR*>(a.A.TB + oo);
     const R inv2s = R(tp.hinv_sus[l]), cap = R(tp.cap[l]);
     LineOut<R, VEC> o;
-    line_prox<R, R, VEC>(P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx, to_end ? Bx : Bo,
-                         to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, inv2s, cap, rp, rt, sv, o);
-    // (networks of the general line model are rejected by the tape)
+    bool special = false;
+    int dci = -1;
+    size_t oh = 0;
+    if constexpr (GEN) {
+      dci = tp.line_dc[l];
+      special = dci >= 0 || tp.chg_ptr[l] != tp.chg_ptr[l + 1];
+    }
+    if (special) {
+      VR Hx{};
+      if (dci >= 0) {
+        oh = ck_off(t, dci, k0, tp.Ldc, tp.Kpp);
+        Hx = *reinterpret_cast<const VR*>(a.A.Hd + oh);
+      }
+      line_prox_gen<R, R, VEC>(tp, l, k0, ok, dci, Hx, td_old, a.A.Tz + size_t(t) * tp.Zc,
+                               nullptr, P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx,
+                               to_end ? Bx : Bo, to_end ? Bo : Bx, tp.Kp, rp, rt, sv, o);
+    } else {
+      line_prox<R, R, VEC>(P, Tm, V1, V2, to_end ? Wx : Wo, to_end ? Wo : Wx, to_end ? Bx : Bo,
+                           to_end ? Bo : Bx, ok, l, td_old, k0, tp.Kp, inv2s, cap, rp, rt, sv, o);
+    }
     NodeAdj<R, VEC> far;
     R fw, ft;
     dev_mean_adj<R>(a, m, t, fw, ft);
@@ -134,30 +158,76 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
     const VR V1b = *reinterpret_cast<const VR*>(a.out.V1 + ol);
     const VR V2b = *reinterpret_cast<const VR*>(a.out.V2 + ol);
     const R iden = R(1) / (R(2) * rp + R(2) * rt * inv2s * inv2s);
-    const R ca = rp * iden, cb = rt * inv2s * iden;
+    const R ca0 = rp * iden, cb0 = rt * inv2s * iden;
     VR Pi, Ti, V1i, V2i;
     double* gc = a.gcap + ol;
+    const R* tzb_out = GEN ? a.out.Tz + size_t(t) * tp.Zc : nullptr;
+    R* tzb_in = GEN ? a.in.Tz + size_t(t) * tp.Zc : nullptr;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       const bool valid = k0 + e < tp.Kp;
       const bool outg = ok.x[e] == l;
+      // this contingency's line model, as line_prox_gen formed it
+      int mode = outg ? 1 : 0, z = -1;
+      R is2 = inv2s, cp = cap, ca = ca0, cb = cb0;
+      bool cap_base = true;  // the capacity is the line's own (not a change's)
+      if (GEN && special) {
+        const int k = k0 + e;
+        R sus = R(tp.sus[l]);
+        cp = R(tp.cap[l]);
+        mode = outg ? 1 : (dci >= 0 ? 2 : 0);
+        for (int c = tp.chg_ptr[l]; c < tp.chg_ptr[l + 1]; ++c) {
+          const LineChg ch = tp.chg[c];
+          if (ch.k > k) break;
+          if (ch.k != k) continue;
+          cap_base = false;
+          if (dci >= 0) {
+            cp = R(ch.cap);
+          } else if (ch.z >= 0) {
+            mode = 1;
+            z = ch.z;
+          } else {
+            sus = R(ch.sus);
+            cp = R(ch.cap);
+          }
+        }
+        is2 = R(0.5) / (mode == 0 ? sus : R(1));
+        const R id = R(1) / (R(2) * rp + R(2) * rt * is2 * is2);
+        ca = rp * id;
+        cb = rt * is2 * id;
+      }
       const R spf = to_end ? far.sp[e] : me.sp[e], sph = to_end ? me.sp[e] : far.sp[e];
       const R sbf = to_end ? far.sb[e] : me.sb[e], sbh = to_end ? me.sb[e] : far.sb[e];
       // adjoints of the line's outputs, including what the node sums took
+      // and what the next iteration read of the held half difference
       R pt = Pb.x[e] + sph - spf;
       const R tt = Tmb.x[e] + sbf + sbh;
       R hb = sbf - sbh;
+      // where the line holds its half phase difference (modes 1 and 2): Hd
+      // for a DC link (outaged or not), Tz for a line a change takes out, Td
+      // for the N-1 outage of an AC line; the next iteration read it there
+      const int src = (GEN && dci >= 0) ? 2 : (mode == 1 ? (z >= 0 ? 3 : 1) : 0);
+      if (src == 1) hb += tdb_out[e];
+      if (GEN && src == 2) hb += a.out.Hd[oh + e];
+      if (GEN && src == 3) hb += tzb_out[z];
       R x1, x2, z1b, z2b;
-      if (outg) {
-        hb += tdb_out[e];
+      if (mode == 1) {
         x1 = R(0.5) * (hb + tt);
         x2 = R(0.5) * (tt - hb);
         z1b = z2b = R(0);
-      } else {
-        pt += hb * inv2s;
-        const bool pass = clip_pass(o.u[e], -cap, cap);
+      } else if (mode == 2) {  // DC link: u = (z2 - z1) / 2, half = (xi1 - xi2) / 2
+        const bool pass = clip_pass(o.u[e], -cp, cp);
         const R ub = pass ? pt : R(0);
-        if (!to_end && valid && !pass) gc[e] += double(o.u[e] > cap ? pt : -pt);
+        if (!to_end && valid && !pass && cap_base) gc[e] += double(o.u[e] > cp ? pt : -pt);
+        z2b = R(0.5) * ub;
+        z1b = -z2b;
+        x1 = R(0.5) * (hb + tt);
+        x2 = R(0.5) * (tt - hb);
+      } else {
+        pt += hb * is2;
+        const bool pass = clip_pass(o.u[e], -cp, cp);
+        const R ub = pass ? pt : R(0);
+        if (!to_end && valid && !pass && cap_base) gc[e] += double(o.u[e] > cp ? pt : -pt);
         z2b = ca * ub;
         z1b = -z2b;
         x1 = cb * ub + R(0.5) * tt;
@@ -167,7 +237,7 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
       const R th1b = sv * v1b, th2b = sv * v2b;
       const R hin = th1b - th2b;
       R pin = z2b - z1b;
-      if (!outg) pin += hin * inv2s;
+      if (mode == 0) pin += hin * is2;
       Pi.x[e] = valid ? pin : R(0);
       Ti.x[e] = valid ? th1b + th2b : R(0);
       V1i.x[e] = valid ? sv * v1b : R(0);
@@ -176,7 +246,14 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
         accW[e] += to_end ? -z2b : -z1b;
         accB[e] += to_end ? x2 - th2b : x1 - th1b;
       }
-      if (!to_end && outg && valid) tdb_in[e] = hin;
+      if (!to_end && valid) {  // the held half difference the line read
+        if (src == 1) tdb_in[e] = hin;
+        if (GEN && src == 3) tzb_in[z] = hin;
+        if (GEN && src == 2) {
+          a.in.Hd[oh + e] = hin;
+          if (outg) tdb_in[e] = R(0);  // (written by the forward, read by no line)
+        }
+      }
     }
     if (!to_end) {  // the from node stores the line's adjoint
       *reinterpret_cast<VR*>(a.in.P + ol) = Pi;
@@ -199,7 +276,7 @@ __device__ inline void adj_vec(const AdjArgs<R>& a, int row, int v, int q0, int 
   *reinterpret_cast<VR*>(a.in.TB + off) = Bi;
 }
 
-template <typename R>
+template <typename R, bool GEN>
 __global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
   const int lpr = a.lanes_per_row, nv = a.nv;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -217,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_sweep(AdjArgs<R> a) {
       const int q0 = a.tp.node_lptr[n], q1 = a.tp.node_lptr[n + 1];
       R mw, mt;
       dev_mean_adj<R>(a, n, t, mw, mt);
-      for (int v = q; v < nv; v += lpr) adj_vec<R>(a, int(row), v, q0, q1, mw, mt, gsp, gsb);
+      for (int v = q; v < nv; v += lpr) adj_vec<R, GEN>(a, int(row), v, q0, q1, mw, mt, gsp, gsb);
     }
     for (int d = lpr >> 1; d > 0; d >>= 1) {
       gsp += __shfl_xor(gsp, d);
@@ -543,7 +620,10 @@ __global__ void __launch_bounds__(kBlock) k_copy(CopyList cl) {
 template <typename R>
 void launch_adj_iteration(const AdjArgs<R>& a, hipStream_t s) {
   const int64_t grid = std::min<int64_t>(a.n_grps, 8192);
-  k_adj_sweep<R><<<int(grid), kBlock, 0, s>>>(a);
+  if (a.tp.Ldc > 0 || a.tp.n_chg > 0)
+    k_adj_sweep<R, true><<<int(grid), kBlock, 0, s>>>(a);
+  else
+    k_adj_sweep<R, false><<<int(grid), kBlock, 0, s>>>(a);
   const int nblk = (a.tp.Jnc + 3) / 4;
   if (nblk == 0) return;
   const int E = (a.tp.T + kWave - 1) / kWave;

@@ -98,7 +98,7 @@ struct TapePlan {
   SnapLayout snap{};
   size_t hist = 0, ckpt = 0, n_ckpt = 0, final_snap = 0, seg = 0;
   size_t masks = 0, mask_words = 0;  // clip masks of every iteration [M][mask_words] (uint32)
-  size_t adj_line[2][4] = {}, adj_td[2] = {}, adj_node[2][3] = {};
+  size_t adj_line[2][4] = {}, adj_td[2] = {}, adj_hd[2] = {}, adj_tz[2] = {}, adj_node[2][3] = {};
   size_t gsp = 0, gsb = 0;
   size_t dev[5] = {};
   size_t ramp_adj = 0, bat_adj = 0, gcap = 0, gload = 0, gpmax = 0;
@@ -1447,6 +1447,8 @@ TapePlan plan_tape(const Inst& s, int precision, int M, int C) {
   for (int b = 0; b < 2; ++b) {
     for (int q = 0; q < 4; ++q) t.adj_line[b][q] = L.take(line);
     t.adj_td[b] = L.take(size_t(s.T) * s.Kpp * S);
+    t.adj_hd[b] = L.take(size_t(s.Ldc) * s.T * s.Kpp * S);
+    t.adj_tz[b] = L.take(size_t(s.Zc) * s.T * S);
     for (int q = 0; q < 3; ++q) t.adj_node[b][q] = L.take(node);
   }
   const size_t nt = size_t(s.N) * s.T * S, jt = size_t(s.Jnc) * s.T * S;
@@ -1531,8 +1533,8 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
   a.A.V1 = sp(2);
   a.A.V2 = sp(3);
   a.A.Td = sp(4);
-  a.A.Hd = nullptr;  // no DC links or changes on a tape
-  a.A.Tz = nullptr;
+  a.A.Hd = sp(15);
+  a.A.Tz = sp(16);
   a.A.U = sp(5);
   a.A.W = sp(6);
   a.A.TB = sp(7);
@@ -1552,6 +1554,8 @@ AdjArgs<R> adj_args(opf_ctx* c, const Inst& s, const char* snap, int ob, double 
     d.V1 = tp(t.adj_line[b][2]);
     d.V2 = tp(t.adj_line[b][3]);
     d.Td = tp(t.adj_td[b]);
+    d.Hd = tp(t.adj_hd[b]);
+    d.Tz = tp(t.adj_tz[b]);
     d.U = tp(t.adj_node[b][0]);
     d.W = tp(t.adj_node[b][1]);
     d.TB = tp(t.adj_node[b][2]);
@@ -1585,9 +1589,6 @@ opf_status tape_check(opf_ctx* c) {
   if (c->bf16_duals) return fail(c, OPF_E_INVALID, "the adjoint needs FP32 or FP64 duals, not BF16");
   if (c->opt.inner_iters > kMaxAdjInner)
     return fail(c, OPF_E_INVALID, "the adjoint supports inner_iters <= 32");
-  if (c->inst[0].Ldc > 0) return fail(c, OPF_E_INVALID, "the adjoint does not support DC links");
-  if (c->inst[0].n_chg > 0)
-    return fail(c, OPF_E_INVALID, "the adjoint does not support per-contingency changes");
   return OPF_OK;
 }
 

@@ -284,6 +284,8 @@ struct AdjBuf {
   R* V1;
   R* V2;
   R* Td;
+  R* Hd;  // DC link half phase differences [T][chunk][Ldc][w] (general line model)
+  R* Tz;  // half differences of lines taken out by changes [T][Zc]
   R* U;
   R* W;
   R* TB;

@@ -117,6 +117,57 @@ def test_fp32_adjoint_close_to_fp64():
         assert e <= 1e-3, (k, e)
 
 
+def general_case(name):
+    """The derivative test grid with the general line model (Section 2.3):
+    DC links with tight capacities (contingency 1 takes the first link out),
+    per-contingency changes (second outages, ratings, susceptances), or both
+    (changes then also reach the links)."""
+    base = tight("adj_gen", N=16, L=24, G=4, D=10, B=2, T=6, K=6, seed=81)
+    if name in ("hvdc", "both"):
+        base = synth.with_dc_links(base, 3, seed=5, cap=(0.1, 0.3))
+    if name in ("changes", "both"):
+        base = synth.with_contingency_changes(base, seed=6, second_outages=2, rating_changes=8,
+                                              sus_changes=3)
+    return base
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("name", ["hvdc", "changes", "both"])
+def test_fp64_adjoint_general_line_model_matches_oracle_autograd(name, case):
+    say(f"[adjoint] fp64 vs oracle autograd, general line model {name}, {case}")
+    inst = general_case(name)
+    w = weights(inst, seed=4)
+    opt = CASES[case]
+    ref, o = oracle_grads(inst, 60, w, 1.0, **opt)
+    got, res, power = gpu_grads(inst, 60, w, 1.0, **opt)
+    assert rel(power, o.dispatch().detach()) <= 1e-10
+    for k in ["load", "cap", "pmax"]:
+        e = rel(got[k], ref[k])
+        say(f"  {k}: relative error {e:.2e} ({int((ref[k] != 0).sum())} nonzero)")
+        assert e <= 1e-9, (k, e)
+    # line clips were active (this grid's generators stay below their limits)
+    assert int((ref["load"] != 0).sum()) > 0 and int((ref["cap"] != 0).sum()) > 0
+    if name != "changes":  # some DC link capacity clipped its flow
+        dc = np.nonzero(np.asarray(inst.line_kind) == 1)[0]
+        assert float(ref["cap"][dc].abs().sum()) > 0.0
+
+
+def test_general_line_model_adjoint_checkpoints_and_fp32():
+    say("[adjoint] general line model: checkpoint intervals, fp32 vs fp64")
+    inst = general_case("both")
+    w = weights(inst, seed=4)
+    opt = CASES["adaptive_penalty"]
+    outs = [gpu_grads(inst, 60, w, 1.0, every=e, **opt)[0] for e in (1, 7, 60)]
+    for o in outs[1:]:
+        for k in o:
+            assert torch.equal(o[k], outs[0][k]), k
+    g32, _, _ = gpu_grads(inst, 60, w, 1.0, dtype="f32", **opt)
+    for k in outs[0]:
+        e = rel(g32[k], outs[0][k])
+        say(f"  {k}: fp32 relative error {e:.2e}")
+        assert e <= 1e-3, (k, e)
+
+
 def test_autograd_function_gives_the_adjoint():
     from paper_2410_17203_amd.autograd import unrolled_dispatch
     say("[adjoint] autograd wrapper")

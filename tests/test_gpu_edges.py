@@ -90,9 +90,8 @@ def test_contingency_count_above_the_limit_is_rejected():
 
 
 def test_dc_link_rules_are_enforced():
-    """Line kinds other than 0/1 are rejected; the adjoint rejects DC links;
-    a DC link's susceptance is ignored (any value, even 0, gives the same
-    iterate)."""
+    """Line kinds other than 0/1 are rejected; a DC link's susceptance is
+    ignored (any value, even 0, gives the same iterate)."""
     from paper_2410_17203_amd import synth
     from paper_2410_17203_amd.binding import OpfError, Solver
     base = synth.make_instance("dc_rules", N=12, L=17, G=4, D=8, B=1, T=4, K=3, seed=5)
@@ -103,8 +102,6 @@ def test_dc_link_rules_are_enforced():
     with pytest.raises(OpfError, match="line kind"):
         Solver(bad, dtype="f64")
     s = Solver(inst, dtype="f64", polish_fp64=0)
-    with pytest.raises(OpfError, match="DC links"):
-        s.tape_forward(10, 5)
     s.iterate(20)
     other = inst.copy()
     other.line_sus = np.asarray(other.line_sus, float).copy()
@@ -120,7 +117,7 @@ def test_dc_link_rules_are_enforced():
 def test_change_rules_are_enforced():
     """Invalid per-contingency changes are rejected (contingency or line out
     of range, a pair given twice, a pair repeating its contingency's outage,
-    negative values); the adjoint rejects networks with changes."""
+    negative values)."""
     from paper_2410_17203_amd import synth
     from paper_2410_17203_amd.binding import OpfError, Solver
     base = synth.make_instance("chg_rules", N=12, L=17, G=4, D=8, B=1, T=4, K=3, seed=5)
@@ -142,11 +139,6 @@ def test_change_rules_are_enforced():
     for inst, msg in bad:
         with pytest.raises(OpfError, match=msg):
             Solver(inst, dtype="f64")
-    s = Solver(with_chg([1, 3], [free[0], free[1]], [0.0, 2.0], [0.0, 0.5]), dtype="f64",
-               polish_fp64=0)
-    with pytest.raises(OpfError, match="per-contingency changes"):
-        s.tape_forward(10, 5)
-    s.close()
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
